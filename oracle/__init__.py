@@ -51,16 +51,16 @@ def lib():
         D = C.c_double
         L.orc_gamma.argtypes = [P, P]
         L.orc_fhat.argtypes = [P, P, P]
-        L.orc_dirac.argtypes = [P, D, D, I, P, P, P, P]
+        L.orc_dirac.argtypes = [P, D, I, P, P, P, P]
         L.orc_hop.argtypes = [P, I, P, P, P]
-        L.orc_clover_inverse.argtypes = [P, D, D, P, P]
+        L.orc_clover_inverse.argtypes = [C.c_long, P, P]
         L.orc_clover_inverse.restype = I
         L.orc_clover_matrices.argtypes = [P, D, D, P, P]
-        L.orc_dirac_dirichlet.argtypes = [P, D, D, I, P, P, P, P, P]
+        L.orc_dirac_dirichlet.argtypes = [P, D, I, P, P, P, P, P]
         L.orc_dirac_dirichlet.restype = I
-        L.orc_sap.argtypes = [P, D, D, I, P, I, I, P, P, P, P, P]
+        L.orc_sap.argtypes = [P, D, I, P, I, I, P, P, P, P, P]
         L.orc_sap.restype = I
-        L.orc_little_op.argtypes = [P, D, D, I, P, I, P, P, P, P]
+        L.orc_little_op.argtypes = [P, D, I, P, I, P, P, P, P]
         L.orc_little_op.restype = I
         L.orc_block_map.argtypes = [P, P, P, P]
         L.orc_block_map.restype = I
@@ -107,35 +107,48 @@ SIGMA_PAIRS = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
 
 @dataclass
 class Operator:
-    """Kappa-normalised O(a)-improved Wilson operator on one gauge field."""
+    """Kappa-normalised O(a)-improved Wilson operator on one gauge field.
+
+    The clover term is held as one 12x12 matrix per site (``Am``), built from
+    the clover field strength ``F``; a caller may pass ``Am`` (and ``Ainv``)
+    explicitly, e.g. rounded to a storage format, to evaluate the same
+    definition on quantised inputs.
+    """
     dims: tuple
     U: np.ndarray
     kappa: float
     csw: float
     bc_t: int = -1
-    F: np.ndarray = field(default=None, repr=False)
+    Am: np.ndarray = field(default=None, repr=False)
     _Ainv: np.ndarray = field(default=None, repr=False)
 
     def __post_init__(self):
         self.dims = tuple(int(d) for d in self.dims)
         self.U = _c128(self.U)
         self.V = synth.volume(self.dims)
-        if self.F is None:
-            self.F = np.zeros((self.V, 6, 3, 3), np.complex128)
-            lib().orc_fhat(_p(_dims(self.dims)), _p(self.U), _p(self.F))
+        self.F = np.zeros((self.V, 6, 3, 3), np.complex128)
+        lib().orc_fhat(_p(_dims(self.dims)), _p(self.U), _p(self.F))
+        if self.Am is None:
+            self.Am = self.clover_matrices()
+        self.Am = _c128(self.Am)
 
     # -- site-local pieces ------------------------------------------------
     @property
     def Ainv(self):
         if self._Ainv is None:
             A = np.zeros((self.V, 12, 12), np.complex128)
-            bad = lib().orc_clover_inverse(_p(_dims(self.dims)), self.kappa, self.csw, _p(self.F), _p(A))
+            bad = lib().orc_clover_inverse(self.V, _p(self.Am), _p(A))
             if bad:
                 raise ZeroDivisionError(f"clover term singular on {bad} sites")
             self._Ainv = A
         return self._Ainv
 
+    @Ainv.setter
+    def Ainv(self, value):
+        self._Ainv = _c128(value)
+
     def clover_matrices(self):
+        """A(x) = 1 + i kappa c_sw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x), 12x12 per site."""
         A = np.zeros((self.V, 12, 12), np.complex128)
         lib().orc_clover_matrices(_p(_dims(self.dims)), self.kappa, self.csw, _p(self.F), _p(A))
         return A
@@ -150,8 +163,7 @@ class Operator:
     def M(self, psi):
         def one(p):
             out = np.empty_like(p)
-            lib().orc_dirac(_p(_dims(self.dims)), self.kappa, self.csw, self.bc_t,
-                            _p(self.U), _p(self.F), _p(p), _p(out))
+            lib().orc_dirac(_p(_dims(self.dims)), self.kappa, self.bc_t, _p(self.U), _p(self.Am), _p(p), _p(out))
             return out
         return self._each(psi, one)
 
@@ -168,8 +180,8 @@ class Operator:
 
         def one(p):
             out = np.empty_like(p)
-            rc = lib().orc_dirac_dirichlet(_p(_dims(self.dims)), self.kappa, self.csw, self.bc_t, _p(b),
-                                           _p(self.U), _p(self.F), _p(p), _p(out))
+            rc = lib().orc_dirac_dirichlet(_p(_dims(self.dims)), self.kappa, self.bc_t, _p(b),
+                                           _p(self.U), _p(self.Am), _p(p), _p(out))
             if rc:
                 raise GeometryError(f"invalid block {block} for lattice {self.dims}")
             return out
@@ -182,8 +194,8 @@ class Operator:
 
         def one(e):
             out = np.empty_like(e)
-            rc = lib().orc_sap(_p(_dims(self.dims)), self.kappa, self.csw, self.bc_t, _p(b), int(ncy), int(nmr),
-                               _p(self.U), _p(self.F), _p(Ainv), _p(e), _p(out))
+            rc = lib().orc_sap(_p(_dims(self.dims)), self.kappa, self.bc_t, _p(b), int(ncy), int(nmr),
+                               _p(self.U), _p(self.Am), _p(Ainv), _p(e), _p(out))
             if rc:
                 raise GeometryError(f"invalid block {block} for lattice {self.dims}")
             return out
@@ -371,8 +383,8 @@ class Deflation:
             phi = block_mgs(vb)
         self.phi = np.ascontiguousarray(phi.reshape(self.Nb, self.Ns, self.Vb * 12), np.complex128)
         self.A = np.zeros((self.Nb, 9, self.Ns, self.Ns), np.complex128)
-        rc = lib().orc_little_op(_p(_dims(op.dims)), op.kappa, op.csw, op.bc_t, _p(_dims(self.block)), self.Ns,
-                                 _p(op.U), _p(op.F), _p(self.phi), _p(self.A))
+        rc = lib().orc_little_op(_p(_dims(op.dims)), op.kappa, op.bc_t, _p(_dims(self.block)), self.Ns,
+                                 _p(op.U), _p(op.Am), _p(self.phi), _p(self.A))
         if rc:
             raise GeometryError("invalid block geometry")
         self._lu = None

@@ -246,10 +246,9 @@ void orc_fhat(const int *dims, const double complex *U, double complex *F /* [V]
 /* Site-local operators                                                 */
 /* ------------------------------------------------------------------ */
 
-/* out = A(x) in, for one site; in/out [4][3] */
-static void clover_site(const lat_t *l, const cplx *F, long x, const cplx *in, cplx *out)
+/* out = A(x) in from the clover field strength (definition above) */
+static void clover_from_fhat(const lat_t *l, const cplx *F, long x, const cplx *in, cplx *out)
 {
-    init_gamma();
     const cplx coef = _Complex_I * l->kappa * l->csw;
     for (int k = 0; k < 12; ++k) out[k] = in[k];
     for (int p = 0; p < 6; ++p) {
@@ -266,6 +265,17 @@ static void clover_site(const lat_t *l, const cplx *F, long x, const cplx *in, c
     }
 }
 
+/* out = A(x) in with the site's stored 12x12 clover matrix Am[x] */
+static void clover_site(const cplx *Am, long x, const cplx *in, cplx *out)
+{
+    const cplx *m = Am + x * 144;
+    for (int i = 0; i < 12; ++i) {
+        cplx s = 0;
+        for (int j = 0; j < 12; ++j) s += m[i * 12 + j] * in[j];
+        out[i] = s;
+    }
+}
+
 /* Full 12x12 matrix A(x), index sc = 3*spin + colour. */
 static void clover_matrix(const lat_t *l, const cplx *F, long x, cplx *Am /* [12][12] */)
 {
@@ -273,7 +283,7 @@ static void clover_matrix(const lat_t *l, const cplx *F, long x, cplx *Am /* [12
     for (int j = 0; j < 12; ++j) {
         memset(e, 0, sizeof(e));
         e[j] = 1;
-        clover_site(l, F, x, e, col);
+        clover_from_fhat(l, F, x, e, col);
         for (int i = 0; i < 12; ++i) Am[i * 12 + j] = col[i];
     }
 }
@@ -328,16 +338,14 @@ static int invert_matrix(cplx *a, int n)
     return rc;
 }
 
-/* Ainv[V][12][12] = A(x)^{-1} at every site.  Returns number of singular sites. */
-int orc_clover_inverse(const int *dims, double kappa, double csw, const double complex *F,
-                       double complex *Ainv)
+/* Ainv[V][12][12] = Am[x]^{-1} at every site.  Returns number of singular sites. */
+int orc_clover_inverse(long V, const double complex *Am, double complex *Ainv)
 {
-    lat_t l = make_lat(dims, kappa, csw, 1);
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
-    for (long x = 0; x < l.V; ++x) {
+    for (long x = 0; x < V; ++x) {
         cplx *m = Ainv + x * 144;
-        clover_matrix(&l, F, x, m);
+        memcpy(m, Am + x * 144, sizeof(cplx) * 144);
         if (invert_matrix(m, 12) != 0) bad++;
     }
     return bad;
@@ -391,14 +399,14 @@ static void hop_site(const lat_t *l, const cplx *U, long x, const cplx *in, cplx
 /* The Dirac operator  M = A - kappa H  (section 2.2, D psi = eta)      */
 /* ------------------------------------------------------------------ */
 
-void orc_dirac(const int *dims, double kappa, double csw, int bc_t, const double complex *U,
-               const double complex *F, const double complex *in, double complex *out)
+void orc_dirac(const int *dims, double kappa, int bc_t, const double complex *U, const double complex *Am,
+               const double complex *in, double complex *out)
 {
-    lat_t l = make_lat(dims, kappa, csw, bc_t);
+    lat_t l = make_lat(dims, kappa, 0, bc_t);
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < l.V; ++x) {
         cplx a[12], h[12];
-        clover_site(&l, F, x, in + x * 12, a);
+        clover_site(Am, x, in + x * 12, a);
         hop_site(&l, U, x, in, h, NULL, 0);
         for (int k = 0; k < 12; ++k) out[x * 12 + k] = a[k] - l.kappa * h[k];
     }
@@ -496,11 +504,10 @@ int orc_block_map(const int *dims, const int *b, long *blk /* [V] */, int *colou
 
 /* Block-restricted (Dirichlet) Dirac operator D_Omega for every block at
  * once: hops whose neighbour lies in another block are dropped. */
-int orc_dirac_dirichlet(const int *dims, double kappa, double csw, int bc_t, const int *b,
-                        const double complex *U, const double complex *F, const double complex *in,
-                        double complex *out)
+int orc_dirac_dirichlet(const int *dims, double kappa, int bc_t, const int *b, const double complex *U,
+                        const double complex *Am, const double complex *in, double complex *out)
 {
-    lat_t l = make_lat(dims, kappa, csw, bc_t);
+    lat_t l = make_lat(dims, kappa, 0, bc_t);
     blocks_t g;
     if (make_blocks(&l, b, &g)) return -2;
     int *blk = (int *)malloc(sizeof(int) * l.V);
@@ -508,7 +515,7 @@ int orc_dirac_dirichlet(const int *dims, double kappa, double csw, int bc_t, con
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < l.V; ++x) {
         cplx a[12], h[12];
-        clover_site(&l, F, x, in + x * 12, a);
+        clover_site(Am, x, in + x * 12, a);
         hop_site(&l, U, x, in, h, blk, 1);
         for (int k = 0; k < 12; ++k) out[x * 12 + k] = a[k] - l.kappa * h[k];
     }
@@ -587,7 +594,7 @@ static void mat12_vec(const cplx *m, const cplx *in, cplx *out)
 }
 
 /* delta = approximate D_Lambda^{-1} rho on one block (local arrays). */
-static void block_solve(const lat_t *l, const cplx *U, const cplx *F, const cplx *Ainv,
+static void block_solve(const lat_t *l, const cplx *U, const cplx *Am, const cplx *Ainv,
                         const blocks_t *g, const blockgeo_t *bg, int nmr, const cplx *rho,
                         cplx *delta, cplx *w1, cplx *w2, cplx *w3, cplx *w4)
 {
@@ -619,7 +626,7 @@ static void block_solve(const lat_t *l, const cplx *U, const cplx *F, const cplx
         for (long j = 0; j < Vb; ++j)
             if (bg->par[j] == 0) {
                 cplx a[12];
-                clover_site(l, F, bg->site[j], w1 + j * 12, a);
+                clover_site(Am, bg->site[j], w1 + j * 12, a);
                 for (int c = 0; c < 12; ++c) {
                     cplx p = a[c] - k * k * w4[j * 12 + c];
                     w4[j * 12 + c] = p;
@@ -649,11 +656,11 @@ static void block_solve(const lat_t *l, const cplx *U, const cplx *F, const cplx
 }
 
 /* psi = M_SAP eta  (n_cy cycles from psi = 0). Returns 0 or -2 (geometry). */
-int orc_sap(const int *dims, double kappa, double csw, int bc_t, const int *b, int ncy, int nmr,
-            const double complex *U, const double complex *F, const double complex *Ainv,
+int orc_sap(const int *dims, double kappa, int bc_t, const int *b, int ncy, int nmr,
+            const double complex *U, const double complex *Am, const double complex *Ainv,
             const double complex *eta, double complex *psi)
 {
-    lat_t l = make_lat(dims, kappa, csw, bc_t);
+    lat_t l = make_lat(dims, kappa, 0, bc_t);
     blocks_t g;
     if (make_blocks(&l, b, &g)) return -2;
     long V = l.V;
@@ -662,7 +669,7 @@ int orc_sap(const int *dims, double kappa, double csw, int bc_t, const int *b, i
     for (int cy = 0; cy < ncy; ++cy) {
         for (int col = 0; col < 2; ++col) {
             /* rho = eta - M psi with the current psi (neighbours included) */
-            orc_dirac(dims, kappa, csw, bc_t, U, F, psi, rho);
+            orc_dirac(dims, kappa, bc_t, U, Am, psi, rho);
             for (long i = 0; i < V * 12; ++i) rho[i] = eta[i] - rho[i];
 #pragma omp parallel
             {
@@ -678,7 +685,7 @@ int orc_sap(const int *dims, double kappa, double csw, int bc_t, const int *b, i
                     cplx *r = wk, *d = wk + g.Vb * 12;
                     for (long j = 0; j < g.Vb; ++j)
                         for (int c = 0; c < 12; ++c) r[j * 12 + c] = rho[bg.site[j] * 12 + c];
-                    block_solve(&l, U, F, Ainv, &g, &bg, nmr, r, d, wk + 2 * g.Vb * 12,
+                    block_solve(&l, U, Am, Ainv, &g, &bg, nmr, r, d, wk + 2 * g.Vb * 12,
                                 wk + 3 * g.Vb * 12, wk + 4 * g.Vb * 12, wk + 5 * g.Vb * 12);
                     for (long j = 0; j < g.Vb; ++j)
                         for (int c = 0; c < 12; ++c) psi[bg.site[j] * 12 + c] += d[j * 12 + c];
@@ -703,11 +710,10 @@ int orc_sap(const int *dims, double kappa, double csw, int bc_t, const int *b, i
 /* block and the two entries add up to its coupling.                    */
 /* ------------------------------------------------------------------ */
 
-int orc_little_op(const int *dims, double kappa, double csw, int bc_t, const int *b, int Ns,
-                  const double complex *U, const double complex *F, const double complex *phi,
-                  double complex *Alit)
+int orc_little_op(const int *dims, double kappa, int bc_t, const int *b, int Ns, const double complex *U,
+                  const double complex *Am, const double complex *phi, double complex *Alit)
 {
-    lat_t l = make_lat(dims, kappa, csw, bc_t);
+    lat_t l = make_lat(dims, kappa, 0, bc_t);
     blocks_t g;
     if (make_blocks(&l, b, &g)) return -2;
     const long Vb = g.Vb;
@@ -734,7 +740,7 @@ int orc_little_op(const int *dims, double kappa, double csw, int bc_t, const int
                     const cplx *own = phi + ((B * Ns + ll) * Vb) * 12;
                     cplx a[12], h[12];
                     /* self: clover + hops inside the block */
-                    clover_site(&l, F, x, own + j * 12, a);
+                    clover_site(Am, x, own + j * 12, a);
                     for (int c = 0; c < 12; ++c) h[c] = 0;
                     for (int mu = 0; mu < 4; ++mu)
                         for (int d = 0; d < 2; ++d) {
