@@ -1,0 +1,220 @@
+/*
+ * dfl.h -- C ABI of the MI355X (gfx950) deflated SAP-GCR Wilson-clover solver.
+ *
+ * The library solves the Dirac equation  D psi = eta  (arXiv:1605.00564,
+ * section 2.2) for the O(a)-improved Wilson (clover) operator by GCR, right
+ * preconditioned with the Schwarz alternating procedure (SAP), optionally
+ * with block-local deflation, and drives the many truncated ("sloppy") and
+ * few exact solves that all-mode averaging needs (section 2.1).
+ *
+ * Operator (the paper names it but does not write it out; the library uses
+ * the kappa-normalised form):  M = A - kappa H  with
+ *   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                     + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu),
+ *   A(x) = 1 + i kappa c_sw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *   Fhat_{mu nu} = (Q_{mu nu} - Q_{mu nu}^+)/8 (four plaquette leaves),
+ * Euclidean chiral basis gamma_0 = [[0,-1],[-1,0]], gamma_k =
+ * [[0,-i sigma_k],[i sigma_k,0]], sigma_{mu nu} = (i/2)[gamma_mu,gamma_nu].
+ * The mass-normalised D = M / (2 kappa); solutions returned are M^{-1} b.
+ *
+ * Conventions shared by every entry point
+ *   - dims = {T, X, Y, Z}; mu = 0 is time; site i = z + Z*(y + Y*(x + X*t)).
+ *   - Vector buffers are caller-owned DEVICE pointers in the canonical layout
+ *     [nrhs][V][4 spin][3 colour] of interleaved complex numbers, complex128
+ *     for QCD_F64 and complex64 for QCD_F32 ("io" precision).  They must not
+ *     alias each other unless a function says so.
+ *   - Links are passed once, from HOST memory, as complex128 [V][4][3][3]
+ *     (U_mu(x) links x to x+mu; SU(3) required because the reduced-precision
+ *     copies store two rows and rebuild the third).
+ *   - Every call is enqueued on the caller's HIP stream; calls that fill host
+ *     arrays (info) synchronise that stream before returning.
+ *   - Handles are library-owned; one host thread at a time per handle.
+ *   - Return codes: 0 ok; QCD_NOCONV (1) = a solve did not reach its target
+ *     (solution, iterations and residual are still written); negative values
+ *     are errors, detailed by qcd_last_error().
+ */
+#ifndef DFL_H
+#define DFL_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QCD_OK 0
+#define QCD_NOCONV 1
+#define QCD_EINVAL (-1)     /* null pointer, bad size or unsupported option */
+#define QCD_EGEOM (-2)      /* block does not divide the lattice, odd block
+                               extent, or an odd number of blocks in a direction */
+#define QCD_ENOMEM (-3)     /* device allocation failed */
+#define QCD_EHIP (-4)       /* HIP runtime error */
+#define QCD_ESINGULAR (-5)  /* singular clover block, little-operator block or
+                               rank-deficient deflation fields */
+#define QCD_ENAN (-6)       /* NaN or Inf in an input or a norm */
+#define QCD_ENOTSET (-7)    /* e.g. deflation requested but not set up */
+
+typedef enum { QCD_F64 = 0, QCD_F32 = 1, QCD_F16 = 2, QCD_BF16 = 3 } qcd_prec;
+
+/* Lattice, operator parameters and the Schwarz block grid.  The block grid
+ * fixes the library's internal site order (block-major, parity split), so a
+ * field handle serves one block size; SAP and deflation use it.  Each block
+ * extent must be even and divide the lattice extent, and the number of
+ * blocks in every direction must be even so that the two-colour checkerboard
+ * of blocks (Omega, Omega*, section 2.2) closes periodically. */
+typedef struct {
+    int dims[4];     /* T, X, Y, Z */
+    int block[4];    /* Schwarz / deflation block extents */
+    double kappa;
+    double csw;
+    int bc_t;        /* -1: antiperiodic in time (fermions), +1: periodic */
+} qcd_lattice;
+
+typedef struct qcd_field_s *qcd_field;
+typedef struct qcd_dfl_s *qcd_dfl;
+
+/* Error text for a return code, and the message of the last failure on the
+ * calling thread (never NULL). */
+const char *qcd_strerror(int code);
+const char *qcd_last_error(void);
+
+/* Build a field handle: copies links_host to the device, packs the storage
+ * copies (FP64 full matrices; FP32, FP16 and BF16 with two rows), builds the
+ * clover term A(x) from the clover leaves in FP64 and the inverse of A on
+ * odd sites (needed by the even-odd block solves), then rounds both to the
+ * reduced storage types.  Singular clover blocks give QCD_ESINGULAR. */
+int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream_t stream,
+                     qcd_field *out);
+int qcd_field_destroy(qcd_field f);
+
+/* out = M in for nrhs vectors (the Dirac operator of section 2.2).
+ * io: QCD_F64 or QCD_F32 canonical vectors.  compute/storage:
+ *   QCD_F64: FP64 links, clover and arithmetic;
+ *   QCD_F32: FP32 links (two rows), clover and arithmetic;
+ *   QCD_F16 / QCD_BF16: FP16 / BF16 links (two rows), FP16 clover, FP32
+ *   arithmetic and FP32 vectors.
+ * in and out must not overlap. */
+int dirac_apply(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
+                hipStream_t stream);
+
+/* Schwarz preconditioner psi = M_SAP eta (section 2.2): ncy cycles starting
+ * from psi = 0; each cycle visits all blocks of colour 0 (Omega) in
+ * parallel, then all blocks of colour 1 (Omega*).  A block visit computes the
+ * block residual eta - M psi with the current neighbour values, solves the
+ * block equation with Dirichlet boundaries approximately by nmr
+ * minimal-residual steps on the even-odd reduced block operator
+ * A_ee - kappa^2 H_eo A_oo^{-1} H_oe, and adds the correction to psi. */
+typedef struct {
+    int ncy;           /* Schwarz cycles (the paper keeps 5) */
+    int nmr;           /* minimal-residual steps per block solve */
+    qcd_prec storage;  /* QCD_F64 (all FP64), QCD_F32, QCD_F16, QCD_BF16 (FP32 arithmetic) */
+} qcd_sap;
+
+int sap_precond(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, qcd_prec io,
+                hipStream_t stream);
+
+/* Block-local deflation (section 2.2): Ns global fields, drawn as complex
+ * Gaussians from the counter-based generator SplitMix64 (key derived from
+ * seed), refined by ninv rounds of the inverse iteration phi <- M_SAP phi
+ * (normalised), restricted to the blocks and orthonormalised per block by
+ * two passes of modified Gram-Schmidt.  The little operator
+ * A_kl = (phi_k, M phi_l) (eq. little) is assembled in FP64 with its
+ * nearest-neighbour block structure, and its diagonal blocks are inverted. */
+typedef struct {
+    int Ns;
+    int ninv;
+    unsigned long long seed;
+    qcd_sap sap;           /* preconditioner used by the inverse iteration */
+} qcd_dfl_params;
+
+int deflation_setup(qcd_field f, const qcd_dfl_params *p, hipStream_t stream, qcd_dfl *out);
+int deflation_destroy(qcd_dfl d);
+/* Deflation fields as complex128 DEVICE buffer [Nb][Ns][Vb][4][3]: block B
+ * in lexicographic order of the block grid, site j of the block in
+ * lexicographic order of local coordinates. */
+int deflation_get_phi(qcd_dfl d, void *phi, hipStream_t stream);
+/* Replace the fields (same layout; must be block-orthonormal) and rebuild
+ * the little operator; lets a caller supply a known basis. */
+int deflation_set_phi(qcd_dfl d, const void *phi, hipStream_t stream);
+/* Little-operator sizes: Nb blocks, Ns fields, N = Nb*Ns. */
+int deflation_dims(qcd_dfl d, int *Nb, int *Ns);
+/* w = A v for nrhs little vectors, complex128 DEVICE [nrhs][Nb][Ns] with the
+ * block order of deflation_get_phi. */
+int little_dirac_apply(qcd_dfl d, const void *v, void *w, int nrhs, hipStream_t stream);
+/* w = A^{-1} v by FP64 GCR on A with block-Jacobi preconditioning, to
+ * relative residual tol (or maxit iterations); iters (host, may be NULL)
+ * receives the iteration count. */
+int little_dirac_solve(qcd_dfl d, const void *v, void *w, int nrhs, double tol, int maxit, int *iters,
+                       hipStream_t stream);
+/* Phi^+ v (restriction, complex128 [nrhs][Nb][Ns]) and Phi c
+ * (prolongation, canonical vectors) for canonical io vectors. */
+int deflation_restrict(qcd_dfl d, const void *v, void *u, int nrhs, qcd_prec io, hipStream_t stream);
+int deflation_prolong(qcd_dfl d, const void *u, void *v, int nrhs, qcd_prec io, hipStream_t stream);
+
+/* GCR solve of M x = b (section 2.2: right-preconditioned GCR on
+ * D M_SAP phi = eta, psi = M_SAP phi), flexible, restarted.
+ * The outer loop keeps x and the residual in FP64 and recomputes
+ * r = b - M x with the FP64 operator at every restart; inside a cycle the
+ * Krylov vectors are stored in FP32, the preconditioner runs at sap.storage
+ * and the Gram-Schmidt coefficients are accumulated in FP64.
+ * With a deflation handle the solution is psi = chi + Phi A^{-1} Phi^+ eta
+ * (eq. deflsoln): GCR starts from the low-mode part and every search
+ * direction is projected by P_R.
+ * Stopping: relative residual ||b - M x||/||b|| <= res (FP64), or exactly
+ * fixed_iters iterations when fixed_iters > 0 (truncated solves), or nmx. */
+typedef struct {
+    int nkv;            /* Krylov vectors per cycle */
+    int nmx;            /* iteration limit */
+    int fixed_iters;    /* > 0: stop after exactly this many iterations */
+    double res;         /* target relative residual */
+    qcd_sap sap;        /* preconditioner */
+    qcd_dfl dfl;        /* NULL: no deflation */
+    double little_tol;  /* relative residual of the little solves */
+    int little_maxit;
+} qcd_gcr;
+
+typedef struct {
+    int status;       /* 0 converged, QCD_NOCONV otherwise */
+    int iters;
+    double rel_res;   /* FP64 ||b - M x|| / ||b|| recomputed at exit */
+} qcd_info;
+
+int gcr_solve(qcd_field f, const qcd_gcr *p, const void *b, void *x, int nrhs, qcd_prec io,
+              qcd_info *info /* host [nrhs] */, hipStream_t stream);
+
+/* All-mode averaging (section 2.1): for every source position g in G the 12
+ * spin-colour point sources eta = delta_{x,x_g} delta_{sc,sc'} are solved
+ * with the sloppy parameters; positions flagged in exact[] are also solved
+ * with the exact parameters.  Positions must map the block checkerboard
+ * onto itself relative to each other (shifts by whole blocks with an even
+ * total number of block steps), so that M_SAP is covariant under the
+ * translations relating them (section 2.2); otherwise QCD_EGEOM.
+ * x_sloppy[g] and x_exact[e] are DEVICE buffers of 12 canonical vectors
+ * (sc = 3*spin + colour) at io precision; e counts flagged positions in order.
+ * batch: number of right-hand sides solved together (0: library choice). */
+typedef struct {
+    int npos;
+    const int *pos;                /* host [npos][4] = (t, x, y, z) */
+    const unsigned char *exact;    /* host [npos], nonzero = also solve exactly */
+    qcd_gcr sloppy, exact_params;
+    int batch;
+} qcd_ama;
+
+int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const *x_exact, qcd_prec io,
+              qcd_info *info_sloppy /* host [npos*12] */, qcd_info *info_exact /* host [nexact*12] */,
+              hipStream_t stream);
+
+/* Kernel timing with HIP events on the launch stream, for measurement.
+ * Classes: 0 Dirac stencil, 1 SAP block sweep, 2 deflation projection and
+ * prolongation, 3 little operator, 4 vector algebra, 5 other. */
+#define QCD_PROF_CLASSES 6
+int qcd_prof_enable(int on);
+int qcd_prof_reset(void);
+/* Total milliseconds and launch count for a class since the last reset
+ * (synchronises the recorded events). */
+int qcd_prof_get(int cls, double *ms, long long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,851 @@
+// Block-local deflation (section 2.2): subspace from Ns global fields
+// restricted to the Schwarz blocks and orthonormalised per block, the little
+// Dirac operator A_kl = (phi_k, M phi_l) (eq. little), restriction Phi^+ v,
+// prolongation Phi c, and the little solve A^{-1} by block-Jacobi GCR.
+#include <cmath>
+
+#include "blas.h"
+#include "dflint.h"
+
+namespace dfl {
+
+qcd_field dfl_field(qcd_dfl d) { return d->f; }
+
+// ---------------------------------------------------------------------------
+// random fields: SplitMix64 counter-based generator with Box-Muller
+// (Steele, Lea, Flood 2014).  Field l, lexicographic site i, component sc is
+// complex number j = (l V + i) 12 + sc; its real and imaginary parts are the
+// cosine and sine branches of Box-Muller on outputs 2j and 2j+1.
+// ---------------------------------------------------------------------------
+__device__ inline unsigned long long sm64(unsigned long long key, unsigned long long n) {
+    unsigned long long z = key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+static unsigned long long sm64_host(unsigned long long key, unsigned long long n) {
+    unsigned long long z = key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_random_fields(float4 *__restrict__ v, unsigned long long key, const int *__restrict__ lex_of,
+                                long V) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= V) return;
+    const int l = blockIdx.y;
+    const long i = lex_of[idx];
+    float c[24];
+    for (int sc = 0; sc < 12; ++sc) {
+        const unsigned long long j = ((unsigned long long)l * V + i) * 12 + sc;
+        const double u1 = 1.0 - (double)(sm64(key, 2 * j) >> 11) * 0x1.0p-53;
+        const double u2 = (double)(sm64(key, 2 * j + 1) >> 11) * 0x1.0p-53;
+        const double r = sqrt(-2.0 * log(u1));
+        const double a = 2.0 * M_PI * u2;
+        c[2 * sc] = (float)(r * cos(a));
+        c[2 * sc + 1] = (float)(r * sin(a));
+    }
+    for (int ch = 0; ch < 6; ++ch)
+        v[((size_t)l * 6 + ch) * V + idx] = make_float4(c[4 * ch], c[4 * ch + 1], c[4 * ch + 2], c[4 * ch + 3]);
+}
+
+// v_r *= 1/sqrt(nrm2_r)
+__global__ void k_normalise(float4 *__restrict__ v, long ne, const double *__restrict__ nrm2) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne) return;
+    const double n2 = nrm2[blockIdx.y];
+    const float s = n2 > 0 ? (float)(1.0 / sqrt(n2)) : 0.f;
+    float4 a = v[(size_t)blockIdx.y * ne + t];
+    v[(size_t)blockIdx.y * ne + t] = make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
+}
+
+// global fields [Ns][6][V] -> block storage phi[B][l][6][2][Vbh]
+__global__ void k_to_blocks(const float4 *__restrict__ v, float4 *__restrict__ phi, const int *__restrict__ boff,
+                            long V, long Vh, int Vbh, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = 12L * Vbh;
+    if (t >= (long)Nb * Ns * per) return;
+    const long q = t % per;
+    const long bl = t / per;
+    const int l = (int)(bl % Ns), B = (int)(bl / Ns);
+    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+    phi[t] = v[((size_t)l * 6 + c) * V + p * Vh + boff[B] + j];
+}
+
+// phi_l of every block as one global FP32 field [6][V]
+__global__ void k_phi_field(const float4 *__restrict__ phi, int l, float4 *__restrict__ out, const int *__restrict__ boff,
+                            long V, long Vh, int Vbh, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = 12L * Vbh;
+    if (t >= (long)Nb * per) return;
+    const int B = (int)(t / per);
+    const long q = t % per;
+    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+    out[(size_t)c * V + p * Vh + boff[B] + j] = phi[((size_t)B * Ns + l) * per + q];
+}
+
+template <int NV>
+__device__ inline void wg_sum(double v[NV], double out[NV]) {
+    __shared__ double sh[NV][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) sh[q][w] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0;
+        for (int k = 0; k < nw; ++k) t += sh[q][k];
+        out[q] = t;
+    }
+    __syncthreads();
+}
+
+// two passes of modified Gram-Schmidt over l inside each block (one workgroup per block)
+__global__ void __launch_bounds__(256) k_block_mgs(float4 *__restrict__ phi, int Ns, int Vbh, int *flag) {
+    const long per = 12L * Vbh;
+    float4 *base = phi + (size_t)blockIdx.x * Ns * per;
+    for (int l = 0; l < Ns; ++l) {
+        float4 *pl = base + (size_t)l * per;
+        double v[1], o[1];
+        v[0] = 0;
+        for (long i = threadIdx.x; i < per; i += blockDim.x) {
+            const float4 a = pl[i];
+            v[0] += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
+        }
+        wg_sum<1>(v, o);
+        const double n0 = sqrt(o[0]);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < l; ++k) {
+                const float4 *pk = base + (size_t)k * per;
+                double d[2] = {0, 0}, od[2];
+                for (long i = threadIdx.x; i < per; i += blockDim.x) {
+                    const float4 a = pk[i], b = pl[i];
+                    d[0] += (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+                    d[1] += (double)a.x * b.y - (double)a.y * b.x + (double)a.z * b.w - (double)a.w * b.z;
+                }
+                wg_sum<2>(d, od);
+                const float cr = (float)od[0], ci = (float)od[1];
+                for (long i = threadIdx.x; i < per; i += blockDim.x) {
+                    const float4 a = pk[i];
+                    float4 b = pl[i];
+                    b.x -= cr * a.x - ci * a.y;
+                    b.y -= cr * a.y + ci * a.x;
+                    b.z -= cr * a.z - ci * a.w;
+                    b.w -= cr * a.w + ci * a.z;
+                    pl[i] = b;
+                }
+                __syncthreads();
+            }
+        v[0] = 0;
+        for (long i = threadIdx.x; i < per; i += blockDim.x) {
+            const float4 a = pl[i];
+            v[0] += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
+        }
+        wg_sum<1>(v, o);
+        const double nl = sqrt(o[0]);
+        if (!(nl > 1e-10 * n0) || !(nl > 0)) {
+            if (threadIdx.x == 0) atomicOr(flag, 2);
+            return;
+        }
+        const float s = (float)(1.0 / nl);
+        for (long i = threadIdx.x; i < per; i += blockDim.x) {
+            float4 a = pl[i];
+            pl[i] = make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
+        }
+        __syncthreads();
+    }
+}
+
+// Direction-resolved operator on a FP32 field (FP64 arithmetic):
+// out[0] = clover + hops inside the block, out[1 + 2 mu + dir] = -kappa times
+// the single hop (mu, dir) when it leaves the block (zero otherwise).
+__global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ in, double2 *__restrict__ out,
+                                                     const void *__restrict__ U, const void *__restrict__ clo,
+                                                     const int *__restrict__ nbr, long V, long Vh, int Vbh,
+                                                     double kappa) {
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= V) return;
+    const long bx = (x >= Vh ? x - Vh : x) / Vbh;
+    cx<double> acc[12], w[9], p[12], h[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
+#define DFL_SPLIT(MU, FWD)                                                                   \
+    {                                                                                        \
+        const int e = nbr[(2 * MU + (FWD ? 0 : 1)) * V + x];                                 \
+        const long y = nb_index(e);                                                          \
+        const long by = (y >= Vh ? y - Vh : y) / Vbh;                                        \
+        Link<LNK_F64>::load(U, V, MU, FWD ? x : y, w);                                       \
+        Spin<float>::load(in, V, y, p);                                                      \
+        const int d = 1 + 2 * MU + (FWD ? 0 : 1);                                            \
+        if (by == bx) {                                                                      \
+            hop<double, MU, FWD>(w, p, nb_sign<double>(e), acc);                             \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = {0, 0};                    \
+        } else {                                                                             \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = {0, 0};                    \
+            hop<double, MU, FWD>(w, p, nb_sign<double>(e), h);                               \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = (-kappa) * h[k];           \
+        }                                                                                    \
+        Spin<double>::store(out + (size_t)d * 12 * V, V, x, h);                              \
+    }
+    DFL_SPLIT(0, true) DFL_SPLIT(0, false) DFL_SPLIT(1, true) DFL_SPLIT(1, false)
+    DFL_SPLIT(2, true) DFL_SPLIT(2, false) DFL_SPLIT(3, true) DFL_SPLIT(3, false)
+#undef DFL_SPLIT
+    Spin<float>::load(in, V, x, p);
+    clover_apply<CLO_F64>(clo, V, x, p, h);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = h[k] - kappa * acc[k];
+    Spin<double>::store(out, V, x, h);
+}
+
+// u[r][B][l] = (phi_{B,l}, v_r) over the block's sites.  One workgroup per
+// (block, rhs); E = float4 (FP32 vector) or double2 (FP64 vector).
+template <class E>
+__device__ inline void rdot(const float4 &f, const E *v, long i0, long i1, double &re, double &im);
+template <>
+__device__ inline void rdot<float4>(const float4 &f, const float4 *v, long i0, long, double &re, double &im) {
+    const float4 b = v[i0];
+    re += (double)f.x * b.x + (double)f.y * b.y + (double)f.z * b.z + (double)f.w * b.w;
+    im += (double)f.x * b.y - (double)f.y * b.x + (double)f.z * b.w - (double)f.w * b.z;
+}
+template <>
+__device__ inline void rdot<double2>(const float4 &f, const double2 *v, long i0, long i1, double &re, double &im) {
+    const double2 a = v[i0], b = v[i1];
+    re += (double)f.x * a.x + (double)f.y * a.y + (double)f.z * b.x + (double)f.w * b.y;
+    im += (double)f.x * a.y - (double)f.y * a.x + (double)f.z * b.y - (double)f.w * b.x;
+}
+
+template <class E>
+__global__ void __launch_bounds__(256) k_restrict(const E *__restrict__ v, const float4 *__restrict__ phi,
+                                                  const int *__restrict__ boff, double2 *__restrict__ u, long V,
+                                                  long Vh, int Vbh, int Ns, int Nb) {
+    const int B = blockIdx.x, r = blockIdx.y;
+    const long per = 12L * Vbh;
+    constexpr int NCH = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4 ? 6 : 12;
+    const E *vr = v + (size_t)r * NCH * V;
+    const long bo = boff[B];
+    for (int l = 0; l < Ns; ++l) {
+        const float4 *pl = phi + ((size_t)B * Ns + l) * per;
+        double d[2] = {0, 0}, od[2];
+        for (long q = threadIdx.x; q < per; q += blockDim.x) {
+            const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+            const long site = p * Vh + bo + j;
+            if (NCH == 6)
+                rdot<E>(pl[q], vr, (long)c * V + site, 0, d[0], d[1]);
+            else
+                rdot<E>(pl[q], vr, (long)(2 * c) * V + site, (long)(2 * c + 1) * V + site, d[0], d[1]);
+        }
+        wg_sum<2>(d, od);
+        if (threadIdx.x == 0) u[((size_t)r * Nb + B) * Ns + l] = make_double2(od[0], od[1]);
+    }
+}
+
+// v_r (op)= sum_l phi_{B,l} c[r][B][l]; MODE 0: v = .., 1: v -= .., 2: v += ..
+template <class E, int MODE>
+__global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4 *__restrict__ phi,
+                                                 const int *__restrict__ boff, const double2 *__restrict__ cf,
+                                                 long V, long Vh, int Vbh, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = 12L * Vbh;
+    if (t >= (long)Nb * per) return;
+    const int r = blockIdx.y;
+    const int B = (int)(t / per);
+    const long q = t % per;
+    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+    const long site = p * Vh + boff[B] + j;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    const double2 *cc = cf + ((size_t)r * Nb + B) * Ns;
+    for (int l = 0; l < Ns; ++l) {
+        const float4 f = phi[((size_t)B * Ns + l) * per + q];
+        const double2 k = cc[l];
+        ar += f.x * k.x - f.y * k.y;
+        ai += f.x * k.y + f.y * k.x;
+        br += f.z * k.x - f.w * k.y;
+        bi += f.z * k.y + f.w * k.x;
+    }
+    constexpr bool F32V = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4;
+    if constexpr (F32V) {
+        float4 *dst = reinterpret_cast<float4 *>(v) + (size_t)r * 6 * V + (size_t)c * V + site;
+        float4 o = MODE == 0 ? make_float4(0, 0, 0, 0) : *dst;
+        const float sg = MODE == 1 ? -1.f : 1.f;
+        *dst = make_float4(o.x + sg * (float)ar, o.y + sg * (float)ai, o.z + sg * (float)br, o.w + sg * (float)bi);
+    } else {
+        double2 *d0 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c) * V + site;
+        double2 *d1 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c + 1) * V + site;
+        double2 o0 = MODE == 0 ? make_double2(0, 0) : *d0, o1 = MODE == 0 ? make_double2(0, 0) : *d1;
+        const double sg = MODE == 1 ? -1.0 : 1.0;
+        *d0 = make_double2(o0.x + sg * ar, o0.y + sg * ai);
+        *d1 = make_double2(o1.x + sg * br, o1.y + sg * bi);
+    }
+}
+
+// w[r][B][k] = sum_d sum_l A[B][d][k][l] v[r][nbr(B,d)][l]
+__global__ void k_little_apply(const double2 *__restrict__ A, const int *__restrict__ bnbr,
+                               const double2 *__restrict__ v, double2 *__restrict__ w, int Nb, int Ns) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)Nb * Ns) return;
+    const int r = blockIdx.y;
+    const int B = (int)(t / Ns), k = (int)(t % Ns);
+    double sr = 0, si = 0;
+    for (int d = 0; d < 9; ++d) {
+        const double2 *a = A + (((size_t)B * 9 + d) * Ns + k) * Ns;
+        const double2 *x = v + ((size_t)r * Nb + bnbr[B * 9 + d]) * Ns;
+        for (int l = 0; l < Ns; ++l) {
+            const double2 aa = a[l], xx = x[l];
+            sr += aa.x * xx.x - aa.y * xx.y;
+            si += aa.x * xx.y + aa.y * xx.x;
+        }
+    }
+    w[(size_t)r * Nb * Ns + t] = make_double2(sr, si);
+}
+
+// z[r][B] = Dinv[B] v[r][B]
+__global__ void k_little_jacobi(const double2 *__restrict__ Dinv, const double2 *__restrict__ v,
+                                double2 *__restrict__ z, int Nb, int Ns) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)Nb * Ns) return;
+    const int r = blockIdx.y;
+    const int B = (int)(t / Ns), k = (int)(t % Ns);
+    const double2 *a = Dinv + ((size_t)B * Ns + k) * Ns;
+    const double2 *x = v + ((size_t)r * Nb + B) * Ns;
+    double sr = 0, si = 0;
+    for (int l = 0; l < Ns; ++l) {
+        const double2 aa = a[l], xx = x[l];
+        sr += aa.x * xx.x - aa.y * xx.y;
+        si += aa.x * xx.y + aa.y * xx.x;
+    }
+    z[(size_t)r * Nb * Ns + t] = make_double2(sr, si);
+}
+
+// Dinv[B] = A[B][0]^{-1}: Gauss-Jordan with partial pivoting, one thread per
+// block, working copy in `work` ([Nb][Ns][Ns])
+__global__ void k_block_inverse(const double2 *__restrict__ A, double2 *__restrict__ Dinv,
+                                double2 *__restrict__ work, int Nb, int Ns, int *flag) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= Nb) return;
+    double2 *a = work + (size_t)B * Ns * Ns;
+    double2 *b = Dinv + (size_t)B * Ns * Ns;
+    const double2 *src = A + (size_t)B * 9 * Ns * Ns;
+    for (int i = 0; i < Ns * Ns; ++i) {
+        a[i] = src[i];
+        b[i] = make_double2((i / Ns) == (i % Ns) ? 1.0 : 0.0, 0.0);
+    }
+    double scale = 0;
+    for (int i = 0; i < Ns * Ns; ++i) scale = fmax(scale, a[i].x * a[i].x + a[i].y * a[i].y);
+    for (int c = 0; c < Ns; ++c) {
+        int p = c;
+        double best = a[c * Ns + c].x * a[c * Ns + c].x + a[c * Ns + c].y * a[c * Ns + c].y;
+        for (int r = c + 1; r < Ns; ++r) {
+            const double v = a[r * Ns + c].x * a[r * Ns + c].x + a[r * Ns + c].y * a[r * Ns + c].y;
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (!(best > 1e-28 * scale)) {
+            atomicOr(flag, 4);
+            return;
+        }
+        if (p != c)
+            for (int k = 0; k < Ns; ++k) {
+                double2 t = a[c * Ns + k];
+                a[c * Ns + k] = a[p * Ns + k];
+                a[p * Ns + k] = t;
+                t = b[c * Ns + k];
+                b[c * Ns + k] = b[p * Ns + k];
+                b[p * Ns + k] = t;
+            }
+        const double2 pv = a[c * Ns + c];
+        const double den = pv.x * pv.x + pv.y * pv.y;
+        const double2 iv = make_double2(pv.x / den, -pv.y / den);
+        for (int k = 0; k < Ns; ++k) {
+            double2 t = a[c * Ns + k];
+            a[c * Ns + k] = make_double2(t.x * iv.x - t.y * iv.y, t.x * iv.y + t.y * iv.x);
+            t = b[c * Ns + k];
+            b[c * Ns + k] = make_double2(t.x * iv.x - t.y * iv.y, t.x * iv.y + t.y * iv.x);
+        }
+        for (int r = 0; r < Ns; ++r) {
+            if (r == c) continue;
+            const double2 f = a[r * Ns + c];
+            if (f.x == 0 && f.y == 0) continue;
+            for (int k = 0; k < Ns; ++k) {
+                const double2 u = a[c * Ns + k], q = b[c * Ns + k];
+                a[r * Ns + k].x -= f.x * u.x - f.y * u.y;
+                a[r * Ns + k].y -= f.x * u.y + f.y * u.x;
+                b[r * Ns + k].x -= f.x * q.x - f.y * q.y;
+                b[r * Ns + k].y -= f.x * q.y + f.y * q.x;
+            }
+        }
+    }
+}
+
+// canonical phi [Nb][Ns][Vb][12] complex128 <-> internal block storage
+__global__ void k_phi_export(const float4 *__restrict__ phi, double2 *__restrict__ out, const int *__restrict__ boff,
+                             const int *__restrict__ loc, long Vh, int Vbh, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over (B, l, p, j)
+    if (t >= (long)Nb * Ns * 2 * Vbh) return;
+    const int j = (int)(t % Vbh), p = (int)((t / Vbh) % 2);
+    const long bl = t / (2 * Vbh);
+    const int l = (int)(bl % Ns), B = (int)(bl / Ns);
+    const long site = p * Vh + boff[B] + j;
+    const int jl = loc[site];
+    const int Vb = 2 * Vbh;
+    const float4 *src = phi + ((size_t)B * Ns + l) * 12 * Vbh;
+    double2 *dst = out + (((size_t)B * Ns + l) * Vb + jl) * 12;
+    for (int c = 0; c < 6; ++c) {
+        const float4 f = src[(size_t)c * 2 * Vbh + p * Vbh + j];
+        dst[2 * c] = make_double2(f.x, f.y);
+        dst[2 * c + 1] = make_double2(f.z, f.w);
+    }
+}
+
+__global__ void k_phi_import(const double2 *__restrict__ in, float4 *__restrict__ phi, const int *__restrict__ boff,
+                             const int *__restrict__ loc, long Vh, int Vbh, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)Nb * Ns * 2 * Vbh) return;
+    const int j = (int)(t % Vbh), p = (int)((t / Vbh) % 2);
+    const long bl = t / (2 * Vbh);
+    const int l = (int)(bl % Ns), B = (int)(bl / Ns);
+    const long site = p * Vh + boff[B] + j;
+    const int jl = loc[site];
+    const int Vb = 2 * Vbh;
+    float4 *dst = phi + ((size_t)B * Ns + l) * 12 * Vbh;
+    const double2 *src = in + (((size_t)B * Ns + l) * Vb + jl) * 12;
+    for (int c = 0; c < 6; ++c) {
+        const double2 a = src[2 * c], b = src[2 * c + 1];
+        dst[(size_t)c * 2 * Vbh + p * Vbh + j] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+int dfl_work(qcd_dfl d, size_t bytes, void **p) {
+    if (bytes > d->lw_bytes) {
+        if (d->lw) {
+            DFL_HIP(hipDeviceSynchronize());
+            DFL_HIP(hipFree(d->lw));
+        }
+        d->lw = nullptr;
+        d->lw_bytes = 0;
+        if (hipMalloc(&d->lw, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(QCD_ENOMEM, "deflation work space allocation failed");
+        }
+        d->lw_bytes = bytes;
+    }
+    *p = d->lw;
+    return 0;
+}
+
+template <class E>
+int restrict_v(qcd_dfl d, const E *v, double2 *u, int n, hipStream_t s) {
+    const Geom &g = d->f->g;
+    ProfScope ps(PROF_DFL, s);
+    k_restrict<E><<<dim3(d->Nb, n), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns, d->Nb);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+template <class E, int MODE>
+int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
+    const Geom &g = d->f->g;
+    ProfScope ps(PROF_DFL, s);
+    const long tot = (long)d->Nb * 12 * g.Vbh;
+    k_prolong<E, MODE><<<dim3(nblocks(tot, 256), n), 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns,
+                                                                   d->Nb);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+int little_apply_dev(qcd_dfl d, const double2 *v, double2 *w, int n, hipStream_t s) {
+    ProfScope ps(PROF_LITTLE, s);
+    const long N = (long)d->Nb * d->Ns;
+    k_little_apply<<<dim3(nblocks(N, 128), n), 128, 0, s>>>(d->A, d->bnbr, v, w, d->Nb, d->Ns);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+int little_jacobi_dev(qcd_dfl d, const double2 *v, double2 *z, int n, hipStream_t s) {
+    ProfScope ps(PROF_LITTLE, s);
+    const long N = (long)d->Nb * d->Ns;
+    k_little_jacobi<<<dim3(nblocks(N, 128), n), 128, 0, s>>>(d->Dinv, v, z, d->Nb, d->Ns);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+// x = A^{-1} u by block-Jacobi preconditioned GCR (FP64).  poll: check the
+// residual on the host after every iteration and stop at tol; otherwise run
+// one cycle of min(maxit, nkv) iterations without host synchronisation.
+int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int maxit, bool poll, int *iters_out,
+                 double *relres_out, hipStream_t s) {
+    const long N = (long)d->Nb * d->Ns;
+    const int nkv = std::max(1, std::min(maxit, 24));
+    const size_t vb = sizeof(double2) * N * n;
+    const size_t need = vb * (2 * (size_t)nkv + 2) + scalar_bytes(n);
+    void *p;
+    DFL_TRY(dfl_work(d, need, &p));
+    double2 *Z = static_cast<double2 *>(p);
+    double2 *W = Z + (size_t)nkv * n * N;
+    double2 *r = W + (size_t)nkv * n * N;
+    double2 *t = r + (size_t)n * N;
+    Scal sc;
+    DFL_TRY(scalar_buffers_at(t + (size_t)n * N, n, sc));
+    std::vector<double> bn(n, 0.0), h(n);
+    auto fetch = [&](const double *dev) -> int {
+        DFL_HIP(hipMemcpyAsync(d->hp, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        DFL_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) h[i] = d->hp[i];
+        return 0;
+    };
+    if (poll) {
+        DFL_TRY(blas_norm2<double2>(u, N, n, sc.part, sc.red, s));
+        DFL_TRY(fetch(sc.red));
+        for (int i = 0; i < n; ++i) bn[i] = std::sqrt(h[i]);
+    }
+    DFL_TRY(blas_zero<double2>(x, N, n, s));
+    DFL_HIP(hipMemcpyAsync(r, u, vb, hipMemcpyDeviceToDevice, s));
+    int iters = 0;
+    double worst = 0;
+    bool done = false;
+    while (!done && iters < maxit) {
+        int k = 0;
+        while (k < nkv && iters < maxit) {
+            double2 *zk = Z + (size_t)k * n * N, *wk = W + (size_t)k * n * N;
+            DFL_TRY(little_jacobi_dev(d, r, zk, n, s));
+            DFL_TRY(little_apply_dev(d, zk, wk, n, s));
+            int bstride = 2;
+            if (k > 0) bstride = blas_multidot<double2>(W, N, n, k, sc.part, sc.red2, s);
+            if (bstride < 0) return bstride;
+            DFL_TRY(blas_gs_sub<double2>(W, r, N, n, k, sc.red2, bstride, sc.part, sc.red, s));
+            DFL_TRY(gcr_scalars(sc.red2, bstride, sc.red, n, k, sc.R, sc.cvec, sc.coef, s));
+            DFL_TRY(blas_scal_update<double2>(wk, r, N, n, sc.coef, sc.part, sc.red, s));
+            ++k;
+            ++iters;
+            if (poll) {
+                DFL_TRY(fetch(sc.red));
+                bool ok = true;
+                worst = 0;
+                for (int i = 0; i < n; ++i) {
+                    const double rel = bn[i] > 0 ? std::sqrt(h[i]) / bn[i] : 0.0;
+                    worst = std::max(worst, rel);
+                    if (!(rel <= tol)) ok = false;
+                }
+                if (ok) {
+                    done = true;
+                    break;
+                }
+            }
+        }
+        DFL_TRY(gcr_trisolve(sc.R, sc.cvec, n, k, sc.alpha, s));
+        DFL_TRY(blas_accum_d(x, Z, N, n, k, sc.alpha, 2 * NKV_MAX, s));
+        if (!poll) break;
+        if (!done && iters < maxit) {  // restart from the true residual
+            DFL_TRY(little_apply_dev(d, x, t, n, s));
+            DFL_TRY(blas_resid(u, t, r, N, n, sc.part, sc.red, s));
+        }
+    }
+    if (iters_out) *iters_out = iters;
+    if (relres_out) *relres_out = worst;
+    return (poll && !done) ? QCD_NOCONV : 0;
+}
+
+// A[:, d, :, l] for every l from the direction-resolved operator
+int build_little(qcd_dfl d, hipStream_t s) {
+    qcd_field f = d->f;
+    const Geom &g = f->g;
+    const long V = g.V;
+    const int Ns = d->Ns, Nb = d->Nb;
+    void *p;
+    const size_t fbytes = sizeof(float4) * 6 * V;
+    const size_t obytes = sizeof(double2) * 12 * V * 9;
+    const size_t ubytes = sizeof(double2) * (size_t)9 * Nb * Ns;
+    DFL_TRY(dfl_work(d, fbytes + obytes + ubytes + sizeof(double2) * (size_t)Nb * Ns * Ns, &p));
+    float4 *fl = static_cast<float4 *>(p);
+    double2 *out9 = reinterpret_cast<double2 *>(static_cast<char *>(p) + fbytes);
+    double2 *u9 = out9 + (size_t)12 * V * 9;
+    double2 *work = u9 + (size_t)9 * Nb * Ns;
+    std::vector<double2> hu((size_t)9 * Nb * Ns);
+    std::vector<double2> hA((size_t)Nb * 9 * Ns * Ns);
+    for (int l = 0; l < Ns; ++l) {
+        {
+            ProfScope ps(PROF_DFL, s);
+            k_phi_field<<<nblocks((long)Nb * 12 * g.Vbh, 256), 256, 0, s>>>(d->phi, l, fl, d->boff, V, g.Vh, g.Vbh, Ns,
+                                                                            Nb);
+            k_dirac_split<<<nblocks(V, 128), 128, 0, s>>>(fl, out9, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, V, g.Vh,
+                                                          g.Vbh, f->lat.kappa);
+        }
+        DFL_HIP(hipGetLastError());
+        // u9[dd][B][k] = (phi_{B,k}, out_dd) ; treat the 9 outputs as 9 right-hand sides
+        DFL_TRY(restrict_v<double2>(d, out9, u9, 9, s));
+        DFL_HIP(hipMemcpyAsync(hu.data(), u9, ubytes, hipMemcpyDeviceToHost, s));
+        DFL_HIP(hipStreamSynchronize(s));
+        for (int dd = 0; dd < 9; ++dd)
+            for (int B = 0; B < Nb; ++B)
+                for (int k = 0; k < Ns; ++k)
+                    hA[(((size_t)B * 9 + dd) * Ns + k) * Ns + l] = hu[((size_t)dd * Nb + B) * Ns + k];
+    }
+    DFL_HIP(hipMemcpyAsync(d->A, hA.data(), sizeof(double2) * hA.size(), hipMemcpyHostToDevice, s));
+    DFL_HIP(hipMemsetAsync(f->flag, 0, sizeof(int), s));
+    k_block_inverse<<<nblocks(Nb, 64), 64, 0, s>>>(d->A, d->Dinv, work, Nb, Ns, f->flag);
+    DFL_HIP(hipGetLastError());
+    int flag = 0;
+    DFL_HIP(hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DFL_HIP(hipStreamSynchronize(s));
+    if (flag) return set_error(QCD_ESINGULAR, "a diagonal block of the little operator is singular");
+    return 0;
+}
+
+void dfl_free(qcd_dfl d) {
+    if (!d) return;
+    (void)hipFree(d->phi);
+    (void)hipFree(d->A);
+    (void)hipFree(d->Dinv);
+    (void)hipFree(d->bnbr);
+    (void)hipFree(d->boff);
+    (void)hipFree(d->loc);
+    (void)hipFree(d->blex);
+    (void)hipFree(d->lw);
+    if (d->hp) (void)hipHostFree(d->hp);
+    delete d;
+}
+
+}  // namespace
+
+int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int maxit, hipStream_t s) {
+    const size_t nv = (size_t)d->Nb * d->Ns * n;
+    void *p;
+    DFL_TRY(field_buffer(d->f, BUF_DFL, 2 * nv * sizeof(double2), &p));
+    double2 *u = static_cast<double2 *>(p), *c = u + nv;
+    DFL_TRY(restrict_v<double2>(d, b, u, n, s));
+    int rc = little_solve(d, u, c, n, tol, maxit, true, nullptr, nullptr, s);
+    if (rc < 0) return rc;
+    return prolong_v<double2, 2>(d, x, c, n, s);
+}
+
+int dfl_project_R(qcd_dfl d, void *z, void *tmp, int n, qcd_prec vec, qcd_prec storage, int maxit, hipStream_t s) {
+    const size_t nv = (size_t)d->Nb * d->Ns * n;
+    void *p;
+    DFL_TRY(field_buffer(d->f, BUF_DFL, 2 * nv * sizeof(double2), &p));
+    double2 *u = static_cast<double2 *>(p), *c = u + nv;
+    DFL_TRY(dirac_internal(d->f, z, tmp, n, vec, storage, s));
+    if (vec == QCD_F32) {
+        DFL_TRY(restrict_v<float4>(d, static_cast<const float4 *>(tmp), u, n, s));
+    } else {
+        DFL_TRY(restrict_v<double2>(d, static_cast<const double2 *>(tmp), u, n, s));
+    }
+    int rc = little_solve(d, u, c, n, 0.0, maxit, false, nullptr, nullptr, s);
+    if (rc < 0) return rc;
+    if (vec == QCD_F32) return prolong_v<float4, 1>(d, static_cast<float4 *>(z), c, n, s);
+    return prolong_v<double2, 1>(d, static_cast<double2 *>(z), c, n, s);
+}
+
+}  // namespace dfl
+
+using namespace dfl;
+
+extern "C" {
+
+int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_dfl *out) {
+    if (!f || !prm || !out) return set_error(QCD_EINVAL, "null argument to deflation_setup");
+    *out = nullptr;
+    const Geom &g = f->g;
+    if (prm->Ns < 1 || prm->Ns > 12 * g.Vb)
+        return set_error(QCD_ESINGULAR, "Ns must be between 1 and 12 times the block volume");
+    if (prm->ninv < 0) return set_error(QCD_EINVAL, "ninv must be >= 0");
+    qcd_dfl d = new qcd_dfl_s();
+    d->f = f;
+    d->params = *prm;
+    d->Ns = prm->Ns;
+    d->Nb = g.Nb;
+    auto fail = [&](int rc) {
+        dfl_free(d);
+        return rc;
+    };
+    const int Ns = d->Ns, Nb = d->Nb;
+    const long V = g.V;
+    // block tables (lexicographic block order)
+    std::vector<int> boff(Nb), bnbr((size_t)Nb * 9), loc(V), blex(V), rank(Nb);
+    {
+        int cnt[2] = {0, 0};
+        for (int B = 0; B < Nb; ++B) {
+            int r = B, sum = 0;
+            for (int m = 3; m >= 0; --m) {
+                sum += r % g.nb[m];
+                r /= g.nb[m];
+            }
+            rank[B] = (sum & 1) * (Nb / 2) + cnt[sum & 1]++;
+            boff[B] = rank[B] * g.Vbh;
+        }
+        for (int B = 0; B < Nb; ++B) {
+            int c[4], r = B;
+            for (int m = 3; m >= 0; --m) {
+                c[m] = r % g.nb[m];
+                r /= g.nb[m];
+            }
+            bnbr[(size_t)B * 9] = B;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int dir = 0; dir < 2; ++dir) {
+                    int cc[4] = {c[0], c[1], c[2], c[3]};
+                    cc[mu] = (cc[mu] + (dir == 0 ? 1 : -1) + g.nb[mu]) % g.nb[mu];
+                    int k = 0;
+                    for (int m = 0; m < 4; ++m) k = k * g.nb[m] + cc[m];
+                    bnbr[(size_t)B * 9 + 1 + 2 * mu + dir] = k;
+                }
+        }
+        for (long i = 0; i < V; ++i) {
+            long r = i;
+            int c[4];
+            for (int m = 3; m >= 0; --m) {
+                c[m] = (int)(r % g.L[m]);
+                r /= g.L[m];
+            }
+            int Bl = 0, l = 0;
+            for (int m = 0; m < 4; ++m) {
+                Bl = Bl * g.nb[m] + c[m] / g.b[m];
+                l = l * g.b[m] + c[m] % g.b[m];
+            }
+            const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+            const long idx = p * g.Vh + (long)rank[Bl] * g.Vbh + (l >> 1);
+            loc[idx] = l;
+            blex[idx] = Bl;
+        }
+    }
+#define DALLOC(ptr, bytes)                                                                 \
+    if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                              \
+        (void)hipGetLastError();                                                          \
+        return fail(set_error(QCD_ENOMEM, "device allocation failed in deflation_setup")); \
+    }
+    DALLOC(d->phi, sizeof(float4) * (size_t)Nb * Ns * 12 * g.Vbh);
+    DALLOC(d->A, sizeof(double2) * (size_t)Nb * 9 * Ns * Ns);
+    DALLOC(d->Dinv, sizeof(double2) * (size_t)Nb * Ns * Ns);
+    DALLOC(d->bnbr, sizeof(int) * (size_t)Nb * 9);
+    DALLOC(d->boff, sizeof(int) * Nb);
+    DALLOC(d->loc, sizeof(int) * V);
+    DALLOC(d->blex, sizeof(int) * V);
+#undef DALLOC
+    if (hipHostMalloc((void **)&d->hp, sizeof(double) * 4096) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(QCD_ENOMEM, "pinned host allocation failed"));
+    }
+    hipError_t e = hipMemcpyAsync(d->bnbr, bnbr.data(), sizeof(int) * bnbr.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->boff, boff.data(), sizeof(int) * Nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->loc, loc.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->blex, blex.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("deflation upload: ") + hipGetErrorString(e)));
+
+    // Ns random global fields, ninv rounds of v <- M_SAP v / ||.||
+    void *vp;
+    int rc = field_buffer(f, BUF_AMA, sizeof(float4) * 6 * V * (size_t)Ns * 2, &vp);
+    if (rc < 0) return fail(rc);
+    float4 *v = static_cast<float4 *>(vp), *w = v + (size_t)6 * V * Ns;
+    const unsigned long long key = sm64_host(prm->seed, 5ULL);   // stream 5: deflation fields
+    k_random_fields<<<dim3(nblocks(V, 256), Ns), 256, 0, s>>>(v, key, f->lex_of, V);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(set_error(QCD_EHIP, hipGetErrorString(e)));
+    void *sp;
+    rc = field_buffer(f, BUF_RED, scalar_bytes(Ns), &sp);
+    if (rc < 0) return fail(rc);
+    Scal sc;
+    scalar_buffers_at(sp, Ns, sc);
+    qcd_sap sap = prm->sap;
+    if (sap.storage == QCD_F64) sap.storage = QCD_F32;   // the fields are refined in FP32
+    for (int it = 0; it < prm->ninv; ++it) {
+        rc = sap_internal(f, &sap, v, w, Ns, s);
+        if (rc < 0) return fail(rc);
+        std::swap(v, w);
+        rc = blas_norm2<float4>(v, 6 * V, Ns, sc.part, sc.red, s);
+        if (rc < 0) return fail(rc);
+        k_normalise<<<dim3(nblocks(6 * V, 256), Ns), 256, 0, s>>>(v, 6 * V, sc.red);
+    }
+    {
+        const long tot = (long)Nb * Ns * 12 * g.Vbh;
+        k_to_blocks<<<nblocks(tot, 256), 256, 0, s>>>(v, d->phi, d->boff, V, g.Vh, g.Vbh, Ns, Nb);
+        (void)hipMemsetAsync(f->flag, 0, sizeof(int), s);
+        k_block_mgs<<<Nb, 256, 0, s>>>(d->phi, Ns, g.Vbh, f->flag);
+        int flag = 0;
+        e = hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("deflation fields: ") + hipGetErrorString(e)));
+        if (flag) return fail(set_error(QCD_ESINGULAR, "deflation fields are linearly dependent on a block"));
+    }
+    rc = build_little(d, s);
+    if (rc < 0) return fail(rc);
+    *out = d;
+    return 0;
+}
+
+int deflation_destroy(qcd_dfl d) {
+    dfl_free(d);
+    return 0;
+}
+
+int deflation_dims(qcd_dfl d, int *Nb, int *Ns) {
+    if (!d || !Nb || !Ns) return set_error(QCD_EINVAL, "null argument to deflation_dims");
+    *Nb = d->Nb;
+    *Ns = d->Ns;
+    return 0;
+}
+
+int deflation_get_phi(qcd_dfl d, void *phi, hipStream_t s) {
+    if (!d || !phi) return set_error(QCD_EINVAL, "null argument to deflation_get_phi");
+    const Geom &g = d->f->g;
+    const long tot = (long)d->Nb * d->Ns * 2 * g.Vbh;
+    k_phi_export<<<nblocks(tot, 256), 256, 0, s>>>(d->phi, static_cast<double2 *>(phi), d->boff, d->loc, g.Vh, g.Vbh,
+                                                   d->Ns, d->Nb);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+int deflation_set_phi(qcd_dfl d, const void *phi, hipStream_t s) {
+    if (!d || !phi) return set_error(QCD_EINVAL, "null argument to deflation_set_phi");
+    const Geom &g = d->f->g;
+    const long tot = (long)d->Nb * d->Ns * 2 * g.Vbh;
+    k_phi_import<<<nblocks(tot, 256), 256, 0, s>>>(static_cast<const double2 *>(phi), d->phi, d->boff, d->loc, g.Vh,
+                                                   g.Vbh, d->Ns, d->Nb);
+    DFL_HIP(hipGetLastError());
+    return build_little(d, s);
+}
+
+int little_dirac_apply(qcd_dfl d, const void *v, void *w, int nrhs, hipStream_t s) {
+    if (!d || !v || !w || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to little_dirac_apply");
+    return little_apply_dev(d, static_cast<const double2 *>(v), static_cast<double2 *>(w), nrhs, s);
+}
+
+int little_dirac_solve(qcd_dfl d, const void *v, void *w, int nrhs, double tol, int maxit, int *iters,
+                       hipStream_t s) {
+    if (!d || !v || !w || nrhs <= 0 || maxit < 1) return set_error(QCD_EINVAL, "bad arguments to little_dirac_solve");
+    double rel = 0;
+    int rc = little_solve(d, static_cast<const double2 *>(v), static_cast<double2 *>(w), nrhs, tol, maxit, true, iters,
+                          &rel, s);
+    if (rc < 0) return rc;
+    DFL_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+int deflation_restrict(qcd_dfl d, const void *v, void *u, int nrhs, qcd_prec io, hipStream_t s) {
+    if (!d || !v || !u || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to deflation_restrict");
+    const size_t nb = spinor_bytes(QCD_F64, d->f->g.V) * nrhs;
+    void *ws;
+    DFL_TRY(field_buffer(d->f, BUF_APPLY, nb, &ws));
+    DFL_TRY(pack_spinor(d->f, v, io, ws, QCD_F64, nrhs, s));
+    return restrict_v<double2>(d, static_cast<const double2 *>(ws), static_cast<double2 *>(u), nrhs, s);
+}
+
+int deflation_prolong(qcd_dfl d, const void *u, void *v, int nrhs, qcd_prec io, hipStream_t s) {
+    if (!d || !v || !u || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to deflation_prolong");
+    const size_t nb = spinor_bytes(QCD_F64, d->f->g.V) * nrhs;
+    void *ws;
+    DFL_TRY(field_buffer(d->f, BUF_APPLY, nb, &ws));
+    DFL_TRY((prolong_v<double2, 0>(d, static_cast<double2 *>(ws), static_cast<const double2 *>(u), nrhs, s)));
+    return unpack_spinor(d->f, ws, QCD_F64, v, io, nrhs, s);
+}
+
+}  // extern "C"

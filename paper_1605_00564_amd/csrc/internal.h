@@ -1,0 +1,435 @@
+// Internal declarations of the gfx950 solver library (not part of the ABI).
+//
+// Device data layout (all fields of one handle share it):
+//   internal site index  idx = p*Vh + B*Vbh + j
+//     p   = site parity (t+x+y+z) mod 2,
+//     B   = Schwarz block, colour-major: blocks of colour 0 (Omega) first,
+//           each colour in lexicographic order of the block grid,
+//     j   = (local lexicographic index within the block) >> 1.
+//   Block extents are even, so block origins have even parity, the local
+//   parity equals the global one, and j enumerates each parity half of a
+//   block exactly once.  A Schwarz block therefore owns two contiguous runs
+//   of Vbh sites, one per parity, and a colour owns two contiguous halves.
+//   Spinor (one right-hand side): 12 complex (spin-major, colour-minor) per
+//   site, stored as chunks of 16 bytes, structure-of-arrays [chunk][V]:
+//   FP64 -> 12 chunks of one complex, FP32 -> 6 chunks of two complex.
+//   Multi-RHS fields are [rhs][chunk][V].
+//   Links: U_mu(x) for the 4 forward directions, [mu][chunk][V]; FP64 keeps
+//   all 9 entries (9 chunks of one complex), FP32 (3 chunks of 16 B) and
+//   FP16/BF16 (3 chunks of 8 B) keep rows 0 and 1; row 2 = conj(row0 x row1).
+//   Clover: per site two Hermitian 6x6 blocks (chirality halves, index
+//   3*(spin mod 2) + colour), 36 reals each: 6 real diagonal entries, then
+//   the 15 upper off-diagonal entries (i<j, row-major) as (re, im).
+//   Chunks never straddle the two halves: FP64 [36][V] of double2, FP32
+//   [18][V] of float4, FP16 [18][V] of 4 halfs (half h = chunks 18h/2...).
+//   The inverse of the odd-site clover blocks uses the same format on the
+//   odd half only ([chunk][Vh], index idx - Vh).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dfl.h"
+
+namespace dfl {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+int set_error(int code, const std::string &msg);
+
+#define DFL_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::dfl::set_error(QCD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define DFL_TRY(call)                \
+    do {                             \
+        int rc_ = (call);            \
+        if (rc_ < 0) return rc_;     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <class R>
+struct cx {
+    R re, im;
+};
+
+template <class R>
+__host__ __device__ inline cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <class R>
+__host__ __device__ inline cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__host__ __device__ inline cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__host__ __device__ inline cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <class R>
+__host__ __device__ inline cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R>
+__host__ __device__ inline cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <class R>
+__host__ __device__ inline cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class R>
+__host__ __device__ inline cx<R> cmulc(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <class R>
+__host__ __device__ inline cx<R> imul(cx<R> a) { return {-a.im, a.re}; }
+template <class R>
+__host__ __device__ inline R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+struct alignas(8) h4 { __half v[4]; };        // 2 complex in FP16
+struct alignas(8) b4 { __hip_bfloat16 v[4]; }; // 2 complex in BF16
+struct alignas(16) h8 { __half v[8]; };       // 4 complex in FP16
+
+enum LinkFmt { LNK_F64 = 0, LNK_F32 = 1, LNK_F16 = 2, LNK_BF16 = 3 };
+enum CloFmt { CLO_F64 = 0, CLO_F32 = 1, CLO_F16 = 2 };
+
+// Spinor storage traits.
+template <class S>
+struct Spin;
+template <>
+struct Spin<double> {
+    static constexpr int NCH = 12;
+    template <class R>
+    __device__ static inline void load(const void *base, long V, long idx, cx<R> v[12]) {
+        const double2 *p = static_cast<const double2 *>(base);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 t = p[k * V + idx];
+            v[k] = {R(t.x), R(t.y)};
+        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long V, long idx, const cx<R> v[12]) {
+        double2 *p = static_cast<double2 *>(base);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k * V + idx] = make_double2(double(v[k].re), double(v[k].im));
+    }
+};
+template <>
+struct Spin<float> {
+    static constexpr int NCH = 6;
+    template <class R>
+    __device__ static inline void load(const void *base, long V, long idx, cx<R> v[12]) {
+        const float4 *p = static_cast<const float4 *>(base);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float4 t = p[c * V + idx];
+            v[2 * c] = {R(t.x), R(t.y)};
+            v[2 * c + 1] = {R(t.z), R(t.w)};
+        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long V, long idx, const cx<R> v[12]) {
+        float4 *p = static_cast<float4 *>(base);
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            p[c * V + idx] = make_float4(float(v[2 * c].re), float(v[2 * c].im), float(v[2 * c + 1].re),
+                                         float(v[2 * c + 1].im));
+    }
+};
+
+// bytes of one spinor (one RHS) in each storage type
+inline size_t spinor_bytes(qcd_prec p, long V) { return (p == QCD_F64 ? 192 : 96) * (size_t)V; }
+
+// Link access: 3x3 matrix W of site idx and direction mu.
+template <int F>
+struct Link;
+template <>
+struct Link<LNK_F64> {
+    template <class R>
+    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
+        const double2 *p = static_cast<const double2 *>(base) + (long)mu * 9 * V;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 t = p[k * V + idx];
+            w[k] = {R(t.x), R(t.y)};
+        }
+    }
+};
+template <class R>
+__device__ inline void rebuild_row2(cx<R> w[9]) {
+    // row2 = conj(row0 x row1)
+    w[6] = conj(w[1] * w[5] - w[2] * w[4]);
+    w[7] = conj(w[2] * w[3] - w[0] * w[5]);
+    w[8] = conj(w[0] * w[4] - w[1] * w[3]);
+}
+template <>
+struct Link<LNK_F32> {
+    template <class R>
+    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
+        const float4 *p = static_cast<const float4 *>(base) + (long)mu * 3 * V;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float4 t = p[c * V + idx];
+            w[2 * c] = {R(t.x), R(t.y)};
+            w[2 * c + 1] = {R(t.z), R(t.w)};
+        }
+        rebuild_row2(w);
+    }
+};
+template <>
+struct Link<LNK_F16> {
+    template <class R>
+    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
+        const h4 *p = static_cast<const h4 *>(base) + (long)mu * 3 * V;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h4 t = p[c * V + idx];
+            w[2 * c] = {R(__half2float(t.v[0])), R(__half2float(t.v[1]))};
+            w[2 * c + 1] = {R(__half2float(t.v[2])), R(__half2float(t.v[3]))};
+        }
+        rebuild_row2(w);
+    }
+};
+template <>
+struct Link<LNK_BF16> {
+    template <class R>
+    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
+        const b4 *p = static_cast<const b4 *>(base) + (long)mu * 3 * V;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b4 t = p[c * V + idx];
+            w[2 * c] = {R(__bfloat162float(t.v[0])), R(__bfloat162float(t.v[1]))};
+            w[2 * c + 1] = {R(__bfloat162float(t.v[2])), R(__bfloat162float(t.v[3]))};
+        }
+        rebuild_row2(w);
+    }
+};
+
+// Clover access: one chirality half (36 reals) of a site's packed clover.
+template <int F>
+struct Clo;
+template <>
+struct Clo<CLO_F64> {
+    template <class R>
+    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
+        const double2 *p = static_cast<const double2 *>(base) + (long)h * 18 * n;
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            double2 t = p[k * n + at];
+            a[2 * k] = R(t.x);
+            a[2 * k + 1] = R(t.y);
+        }
+    }
+};
+template <>
+struct Clo<CLO_F32> {
+    template <class R>
+    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
+        const float4 *p = static_cast<const float4 *>(base) + (long)h * 9 * n;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float4 t = p[k * n + at];
+            a[4 * k] = R(t.x);
+            a[4 * k + 1] = R(t.y);
+            a[4 * k + 2] = R(t.z);
+            a[4 * k + 3] = R(t.w);
+        }
+    }
+};
+template <>
+struct Clo<CLO_F16> {
+    template <class R>
+    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
+        const h4 *p = static_cast<const h4 *>(base) + (long)h * 9 * n;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            h4 t = p[k * n + at];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[4 * k + e] = R(__half2float(t.v[e]));
+        }
+    }
+};
+
+// out = H v for one packed Hermitian 6x6 block h (36 reals) and 6-vector v.
+template <class R>
+__device__ inline void herm6_apply(const R *h, const cx<R> v[6], cx<R> out[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) out[i] = h[i] * v[i];
+    int m = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+            cx<R> a = {h[6 + 2 * m], h[7 + 2 * m]};
+            out[i] = out[i] + a * v[j];
+            out[j] = out[j] + cmulc(a, v[i]);
+            ++m;
+        }
+}
+
+// out = A v for the clover of site `at` of a table with n entries, read and
+// applied one chirality half at a time.
+template <int CF, class R>
+__device__ inline void clover_apply(const void *clo, long n, long at, const cx<R> v[12], cx<R> out[12]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        R a[36];
+        Clo<CF>::load_half(clo, n, at, h, a);
+        herm6_apply(a, v + 6 * h, out + 6 * h);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// hopping term pieces: (1 + s gamma_mu) W psi accumulated into acc, with the
+// chiral-basis spin projection (two colour vectors h0, h1 carry the result).
+// ---------------------------------------------------------------------------
+template <class R, int MU, int S>
+__device__ inline void project(const cx<R> p[12], cx<R> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+        if (MU == 0) {
+            h[c] = S > 0 ? p0 - p2 : p0 + p2;
+            h[3 + c] = S > 0 ? p1 - p3 : p1 + p3;
+        } else if (MU == 1) {
+            h[c] = S > 0 ? p0 - imul(p3) : p0 + imul(p3);
+            h[3 + c] = S > 0 ? p1 - imul(p2) : p1 + imul(p2);
+        } else if (MU == 2) {
+            h[c] = S > 0 ? p0 - p3 : p0 + p3;
+            h[3 + c] = S > 0 ? p1 + p2 : p1 - p2;
+        } else {
+            h[c] = S > 0 ? p0 - imul(p2) : p0 + imul(p2);
+            h[3 + c] = S > 0 ? p1 + imul(p3) : p1 - imul(p3);
+        }
+    }
+}
+
+template <class R, int MU, int S>
+__device__ inline void reconstruct_add(const cx<R> g[6], R sign, cx<R> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> g0 = sign * g[c], g1 = sign * g[3 + c];
+        acc[c] = acc[c] + g0;
+        acc[3 + c] = acc[3 + c] + g1;
+        if (MU == 0) {  // (h0, h1, -s h0, -s h1)
+            acc[6 + c] = S > 0 ? acc[6 + c] - g0 : acc[6 + c] + g0;
+            acc[9 + c] = S > 0 ? acc[9 + c] - g1 : acc[9 + c] + g1;
+        } else if (MU == 1) {  // (h0, h1, i s h1, i s h0)
+            acc[6 + c] = S > 0 ? acc[6 + c] + imul(g1) : acc[6 + c] - imul(g1);
+            acc[9 + c] = S > 0 ? acc[9 + c] + imul(g0) : acc[9 + c] - imul(g0);
+        } else if (MU == 2) {  // (h0, h1, s h1, -s h0)
+            acc[6 + c] = S > 0 ? acc[6 + c] + g1 : acc[6 + c] - g1;
+            acc[9 + c] = S > 0 ? acc[9 + c] - g0 : acc[9 + c] + g0;
+        } else {  // (h0, h1, i s h0, -i s h1)
+            acc[6 + c] = S > 0 ? acc[6 + c] + imul(g0) : acc[6 + c] - imul(g0);
+            acc[9 + c] = S > 0 ? acc[9 + c] - imul(g1) : acc[9 + c] + imul(g1);
+        }
+    }
+}
+
+// g = W h (DAG=false) or W^+ h (DAG=true) on both colour vectors of h.
+template <class R, bool DAG>
+__device__ inline void su3_mul2(const cx<R> w[9], const cx<R> h[6], cx<R> g[6]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> acc = {R(0), R(0)};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc = acc + (DAG ? cmulc(w[b * 3 + a], h[3 * s + b]) : w[a * 3 + b] * h[3 * s + b]);
+            g[3 * s + a] = acc;
+        }
+}
+
+// acc += sign * (1 - gamma_mu) U psi   (forward hop)  or
+// acc += sign * (1 + gamma_mu) U^+ psi (backward hop)
+template <class R, int MU, bool FWD>
+__device__ inline void hop(const cx<R> w[9], const cx<R> psi[12], R sign, cx<R> acc[12]) {
+    constexpr int S = FWD ? -1 : +1;
+    cx<R> h[6], g[6];
+    project<R, MU, S>(psi, h);
+    su3_mul2<R, !FWD>(w, h, g);
+    reconstruct_add<R, MU, S>(g, sign, acc);
+}
+
+// neighbour table entries: bit 31 marks the antiperiodic time-boundary sign
+__device__ inline long nb_index(int e) { return (long)(e & 0x7fffffff); }
+template <class R>
+__device__ inline R nb_sign(int e) { return e < 0 ? R(-1) : R(1); }
+
+// ---------------------------------------------------------------------------
+// geometry and the field handle
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4], b[4], nb[4];
+    long V, Vh;
+    int Vb, Vbh, Nb;
+};
+
+}  // namespace dfl
+
+struct qcd_field_s {
+    qcd_lattice lat;
+    dfl::Geom g;
+    int device = 0;
+    int *nbr = nullptr;      // [8][V], direction d = 2*mu + (0 fwd | 1 bwd)
+    int *int_of = nullptr;   // [V] lexicographic -> internal
+    int *lex_of = nullptr;   // [V] internal -> lexicographic
+    void *U[4] = {nullptr, nullptr, nullptr, nullptr};      // by LinkFmt
+    void *clo[3] = {nullptr, nullptr, nullptr};             // by CloFmt, all sites
+    void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
+    // scratch buffers owned by the handle, one per purpose, grown on demand
+    void *buf[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t buf_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int *flag = nullptr;     // device status word
+};
+
+namespace dfl {
+
+// grow-only device scratch of a field handle, one buffer per purpose
+enum BufSlot { BUF_APPLY = 0, BUF_SAP = 1, BUF_GCR = 2, BUF_GCR_IO = 3, BUF_DFL = 4, BUF_AMA = 5, BUF_RED = 6, BUF_SAP_IO = 7 };
+int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
+
+// Profiling of kernel classes with HIP events.
+enum ProfClass { PROF_DIRAC = 0, PROF_SAP = 1, PROF_DFL = 2, PROF_LITTLE = 3, PROF_BLAS = 4, PROF_OTHER = 5 };
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfScope(int cls, hipStream_t s);
+    ~ProfScope();
+};
+
+// link / clover storage chosen for a precision request
+inline LinkFmt link_fmt(qcd_prec p) {
+    return p == QCD_F64 ? LNK_F64 : p == QCD_F32 ? LNK_F32 : p == QCD_F16 ? LNK_F16 : LNK_BF16;
+}
+inline CloFmt clo_fmt(qcd_prec p) { return p == QCD_F64 ? CLO_F64 : p == QCD_F32 ? CLO_F32 : CLO_F16; }
+
+// --- internal operations (device pointers in the internal layout) ---------
+// out = M in on internal vectors; nrhs fields of type S (double or float)
+int dirac_internal(qcd_field f, const void *in, void *out, int nrhs, qcd_prec vec, qcd_prec storage,
+                   hipStream_t s);
+// psi = M_SAP eta on internal vectors (FP32 vectors unless sap.storage == F64)
+int sap_internal(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, hipStream_t s);
+// GCR on FP64 internal vectors b -> x (info: host array of n, may be null)
+int gcr_internal(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, qcd_info *info,
+                 hipStream_t s);
+// canonical <-> internal conversion; canon is complex128 (F64) or complex64 (F32)
+int pack_spinor(qcd_field f, const void *canon, qcd_prec io, void *internal, qcd_prec vec, int nrhs,
+                hipStream_t s);
+int unpack_spinor(qcd_field f, const void *internal, qcd_prec vec, void *canon, qcd_prec io, int nrhs,
+                  hipStream_t s);
+
+// launch geometry helper: grid of g workgroups over n items
+inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace dfl

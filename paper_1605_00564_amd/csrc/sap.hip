@@ -1,0 +1,361 @@
+// Schwarz alternating procedure (SAP) on the block checkerboard.
+//
+// One launch = one colour sweep: every workgroup owns one Schwarz block of
+// that colour and one right-hand side.  It forms the block residual
+// rho = eta - M psi (neighbour values from the other colour), solves the
+// Dirichlet block equation approximately with nmr minimal-residual steps on
+// the even-odd reduced block operator
+//     Dhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe
+// and adds the correction to psi.  Thread t owns the even site j = t and the
+// odd site j = t of the block (and j = t + NT when KS = 2).  The two
+// exchange vectors of the MinRes iteration (r on even sites, t = A_oo^{-1}
+// H_oe r on odd sites) live in LDS when they fit, else in a per-workgroup
+// global buffer; everything else stays in registers.
+#include "internal.h"
+
+namespace dfl {
+
+template <class R>
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// acc = sum over hops that stay inside the block (Dirichlet boundary) of the
+// hopping term applied to the exchange buffer buf (opposite parity sites).
+template <class R, int LF>
+__device__ inline void block_hop(const void *U, const int *nbr, long V, long Vh, long x, long boff, int Vbh,
+                                 const cx<R> *buf, cx<R> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+    cx<R> w[9], p[12];
+#define DFL_BHOP(MU)                                                                  \
+    {                                                                                 \
+        const int ef = nbr[(2 * MU) * V + x];                                         \
+        long yf = nb_index(ef);                                                       \
+        long lf = (yf >= Vh ? yf - Vh : yf) - boff;                                   \
+        if (lf >= 0 && lf < Vbh) {                                                    \
+            Link<LF>::load(U, V, MU, x, w);                                           \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lf];  \
+            hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);                              \
+        }                                                                             \
+        const int eb = nbr[(2 * MU + 1) * V + x];                                     \
+        long yb = nb_index(eb);                                                       \
+        long lb = (yb >= Vh ? yb - Vh : yb) - boff;                                   \
+        if (lb >= 0 && lb < Vbh) {                                                    \
+            Link<LF>::load(U, V, MU, yb, w);                                          \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lb];  \
+            hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);                             \
+        }                                                                             \
+    }
+    DFL_BHOP(0)
+    DFL_BHOP(1)
+    DFL_BHOP(2)
+    DFL_BHOP(3)
+#undef DFL_BHOP
+}
+
+// (M psi)(x) with the full neighbourhood (neighbours read from global psi)
+template <class S, class R, int LF, int CF>
+__device__ inline void full_dirac_site(const void *psi, const void *U, const void *clo, const int *nbr, long V,
+                                       long x, R kappa, cx<R> out[12]) {
+    cx<R> acc[12], w[9], p[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+#define DFL_FHOP(MU)                                          \
+    {                                                         \
+        const int ef = nbr[(2 * MU) * V + x];                 \
+        Link<LF>::load(U, V, MU, x, w);                       \
+        Spin<S>::load(psi, V, nb_index(ef), p);               \
+        hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);          \
+        const int eb = nbr[(2 * MU + 1) * V + x];             \
+        Link<LF>::load(U, V, MU, nb_index(eb), w);            \
+        Spin<S>::load(psi, V, nb_index(eb), p);               \
+        hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);         \
+    }
+    DFL_FHOP(0)
+    DFL_FHOP(1)
+    DFL_FHOP(2)
+    DFL_FHOP(3)
+#undef DFL_FHOP
+    Spin<S>::load(psi, V, x, p);
+    clover_apply<CF>(clo, V, x, p, out);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = out[k] - kappa * acc[k];
+}
+
+template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+    k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, const void *__restrict__ U,
+                const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr, long V,
+                long Vh, int Vbh, int nbc, int colour, R kappa, int nmr, int first, cx<R> *gbuf) {
+    extern __shared__ unsigned char dsm[];
+    __shared__ R red[16][3];
+    const int NT = blockDim.x;
+    const int tid = threadIdx.x;
+    const int rhs = blockIdx.y;
+    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
+    const void *eta = static_cast<const char *>(eta_all) + rhs * fs;
+    void *psi = static_cast<char *>(psi_all) + rhs * fs;
+    const long B = (long)colour * nbc + blockIdx.x;
+    const long boff = B * Vbh;
+    cx<R> *Rb, *Tb;
+    if (LDS) {
+        Rb = reinterpret_cast<cx<R> *>(dsm);
+    } else {
+        Rb = gbuf + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (size_t)24 * Vbh;
+    }
+    Tb = Rb + 12 * Vbh;
+
+    cx<R> xe[KS][12];
+    // ---- block residual rho = eta - M psi: rho_e into R, s_o = A_oo^{-1} rho_o into T ----
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int j = tid + k * NT;
+        if (j < Vbh) {
+            const long xe_i = boff + j, xo_i = Vh + boff + j;
+            cx<R> e[12], m[12];
+            Spin<S>::load(eta, V, xe_i, e);
+            if (!first) {
+                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xe_i, kappa, m);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = e[c];
+            Spin<S>::load(eta, V, xo_i, e);
+            if (!first) {
+                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xo_i, kappa, m);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
+            }
+            clover_apply<CF>(cinv, Vh, boff + j, e, m);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = m[c];
+        }
+    }
+    __syncthreads();
+    // ---- r = rhat_e = rho_e + kappa H_eo s_o ; x_e = 0 ; psi_o += s_o ----
+    // (every read of this block's psi happened before the barrier above, and
+    //  no other workgroup of this colour reads this block)
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int j = tid + k * NT;
+        if (j < Vbh) {
+            cx<R> acc[12], q[12];
+            block_hop<R, LF>(U, nbr, V, Vh, boff + j, boff, Vbh, Tb, acc);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                Rb[c * Vbh + j] = Rb[c * Vbh + j] + kappa * acc[c];
+                xe[k][c] = {R(0), R(0)};
+            }
+            const long xo_i = Vh + boff + j;
+            if (first) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = Tb[c * Vbh + j];
+            } else {
+                Spin<S>::load(psi, V, xo_i, q);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = q[c] + Tb[c * Vbh + j];
+            }
+            Spin<S>::store(psi, V, xo_i, q);
+        }
+    }
+    __syncthreads();
+    const R k2 = kappa * kappa;
+    for (int it = 0; it < nmr; ++it) {
+        // t_o = A_oo^{-1} H_oe r
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int j = tid + k * NT;
+            if (j < Vbh) {
+                cx<R> acc[12], t[12];
+                block_hop<R, LF>(U, nbr, V, Vh, Vh + boff + j, boff, Vbh, Rb, acc);
+                clover_apply<CF>(cinv, Vh, boff + j, acc, t);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = t[c];
+            }
+        }
+        __syncthreads();
+        // p = A_ee r - kappa^2 H_eo t ; alpha = (p, r) / (p, p)
+        cx<R> p[KS][12];
+        R pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int j = tid + k * NT;
+            if (j < Vbh) {
+                cx<R> acc[12], r[12];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) r[c] = Rb[c * Vbh + j];
+                clover_apply<CF>(clo, V, boff + j, r, p[k]);
+                block_hop<R, LF>(U, nbr, V, Vh, boff + j, boff, Vbh, Tb, acc);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    p[k][c] = p[k][c] - k2 * acc[c];
+                    const cx<R> q = cmulc(p[k][c], Rb[c * Vbh + j]);
+                    pr_re += q.re;
+                    pr_im += q.im;
+                    pp += norm2(p[k][c]);
+                }
+            }
+        }
+        pr_re = wave_sum(pr_re);
+        pr_im = wave_sum(pr_im);
+        pp = wave_sum(pp);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = pr_re;
+            red[tid >> 6][1] = pr_im;
+            red[tid >> 6][2] = pp;
+        }
+        __syncthreads();
+        R s0 = 0, s1 = 0, s2 = 0;
+        const int nw = (NT + 63) >> 6;
+        for (int w = 0; w < nw; ++w) {
+            s0 += red[w][0];
+            s1 += red[w][1];
+            s2 += red[w][2];
+        }
+        const cx<R> alpha = s2 > R(0) ? cx<R>{s0 / s2, s1 / s2} : cx<R>{R(0), R(0)};
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int j = tid + k * NT;
+            if (j < Vbh) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const cx<R> rc = Rb[c * Vbh + j];
+                    xe[k][c] = xe[k][c] + alpha * rc;
+                    Rb[c * Vbh + j] = it + 1 < nmr ? rc - alpha * p[k][c] : xe[k][c];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (nmr == 0) {
+        // x_e = 0: publish it for the back substitution
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int j = tid + k * NT;
+            if (j < Vbh)
+#pragma unroll
+                for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = {R(0), R(0)};
+        }
+        __syncthreads();
+    }
+    // ---- psi_o += kappa A_oo^{-1} H_oe x_e ; psi_e += x_e ----
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int j = tid + k * NT;
+        if (j < Vbh) {
+            const long xe_i = boff + j, xo_i = Vh + boff + j;
+            cx<R> acc[12], t[12], q[12];
+            block_hop<R, LF>(U, nbr, V, Vh, xo_i, boff, Vbh, Rb, acc);
+            clover_apply<CF>(cinv, Vh, boff + j, acc, t);
+            Spin<S>::load(psi, V, xo_i, q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) q[c] = q[c] + kappa * t[c];
+            Spin<S>::store(psi, V, xo_i, q);
+            if (first) {
+                Spin<S>::store(psi, V, xe_i, xe[k]);
+            } else {
+                Spin<S>::load(psi, V, xe_i, q);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = q[c] + xe[k][c];
+                Spin<S>::store(psi, V, xe_i, q);
+            }
+        }
+    }
+}
+
+// psi = 0 on the sites of one colour (the first sweep writes the other colour)
+template <class S>
+__global__ void k_zero_colour(void *psi_all, long V, long Vh, long half, long cstart) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * half) return;
+    const long idx = (t < half ? 0 : Vh) + cstart + (t < half ? t : t - half);
+    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
+    cx<float> z[12];
+    for (int c = 0; c < 12; ++c) z[c] = {0.f, 0.f};
+    Spin<S>::store(static_cast<char *>(psi_all) + blockIdx.y * fs, V, idx, z);
+}
+
+template <class S, class R, int LF, int CF>
+static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, int nrhs, hipStream_t s) {
+    const Geom &g = f->g;
+    const int Vbh = g.Vbh;
+    const int nbc = g.Nb / 2;
+    const size_t lds = (size_t)24 * Vbh * sizeof(cx<R>);
+    const bool use_lds = lds <= 150 * 1024;
+    int NT = ((Vbh + 63) / 64) * 64;
+    int KS = 1;
+    if (NT > 1024) {
+        NT = 1024;
+        KS = (Vbh + NT - 1) / NT;
+    }
+    if (KS > 2) return set_error(QCD_EINVAL, "Schwarz block too large (more than 4096 sites)");
+    cx<R> *gbuf = nullptr;
+    if (!use_lds) {
+        void *p;
+        DFL_TRY(field_buffer(f, BUF_SAP, (size_t)nbc * nrhs * lds, &p));
+        gbuf = static_cast<cx<R> *>(p);
+    }
+    const R kappa = (R)f->lat.kappa;
+    const long half = (long)nbc * Vbh;
+    ProfScope ps(PROF_SAP, s);
+    // colour 1 sites must start from zero; colour 0 is written by the first sweep
+    k_zero_colour<S><<<dim3(nblocks(2 * half, 256), nrhs), 256, 0, s>>>(psi, g.V, g.Vh, half, half);
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int col = 0; col < 2; ++col) {
+            const int first = (cy == 0 && col == 0) ? 1 : 0;
+            dim3 grid(nbc, nrhs);
+#define DFL_SAP_LAUNCH(LDSV, KSV, MAXT)                                                                        \
+    {                                                                                                          \
+        auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT>;                                                \
+        size_t sh = LDSV ? lds : 0;                                                                            \
+        if (LDSV && sh > 64 * 1024) (void)hipFuncSetAttribute((const void *)kern,                              \
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
+        kern<<<grid, NT, sh, s>>>(eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, g.V, g.Vh, Vbh, nbc, col, \
+                                  kappa, nmr, first, gbuf);                                                    \
+    }
+            if (use_lds) {
+                if (NT <= 256) DFL_SAP_LAUNCH(true, 1, 256)
+                else DFL_SAP_LAUNCH(true, 1, 1024)
+            } else {
+                if (KS == 1) DFL_SAP_LAUNCH(false, 1, 1024)
+                else DFL_SAP_LAUNCH(false, 2, 1024)
+            }
+#undef DFL_SAP_LAUNCH
+        }
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+int sap_internal(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, hipStream_t s) {
+    if (sap->ncy < 1 || sap->nmr < 0) return set_error(QCD_EINVAL, "SAP needs ncy >= 1 and nmr >= 0");
+    switch (sap->storage) {
+        case QCD_F64: return run_sap<double, double, LNK_F64, CLO_F64>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_F32: return run_sap<float, float, LNK_F32, CLO_F32>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_F16: return run_sap<float, float, LNK_F16, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_BF16: return run_sap<float, float, LNK_BF16, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        default: return set_error(QCD_EINVAL, "bad SAP storage precision");
+    }
+}
+
+}  // namespace dfl
+
+using namespace dfl;
+
+extern "C" int sap_precond(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, qcd_prec io,
+                           hipStream_t s) {
+    if (!f || !sap || !eta || !psi || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to sap_precond");
+    if (io != QCD_F64 && io != QCD_F32) return set_error(QCD_EINVAL, "io precision must be F64 or F32");
+    const qcd_prec vec = sap->storage == QCD_F64 ? QCD_F64 : QCD_F32;
+    const size_t nb = spinor_bytes(vec, f->g.V) * nrhs;
+    void *ws;
+    DFL_TRY(field_buffer(f, BUF_SAP_IO, 2 * nb, &ws));
+    char *a = static_cast<char *>(ws), *b = a + nb;
+    DFL_TRY(pack_spinor(f, eta, io, a, vec, nrhs, s));
+    DFL_TRY(sap_internal(f, sap, a, b, nrhs, s));
+    DFL_TRY(unpack_spinor(f, b, vec, psi, io, nrhs, s));
+    return 0;
+}

@@ -1,0 +1,154 @@
+"""GPU parity of the stencil and the Schwarz preconditioner against the oracle.
+
+FP64 paths must agree to 1e-12 relative per application; reduced-precision
+storage (FP32, FP16, BF16 links and clover, FP32 arithmetic) to 1e-5 per
+operator application against the oracle evaluated on identically quantised
+inputs.  M_SAP eta chains about n_cy (n_mr + 2) = 30 FP32 operator
+applications with data-dependent minimal-residual coefficients, so its FP32
+rounding bound is SAP_TOL = 30 x 1e-6 (a single FP32 application rounds to
+about 1e-6 relative here, well inside the 1e-5 per-application bound).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import quant
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+SAP_TOL = 3e-5
+
+
+def _gpu():
+    import torch
+    import paper_1605_00564_amd as dfl
+    return torch, dfl
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).reshape(-1)) / np.linalg.norm(b.reshape(-1)))
+
+
+class Case:
+    def __init__(self, dims, block, eps, kappa, csw, bc_t=-1, seed=1):
+        torch, dfl = _gpu()
+        self.dims, self.block = dims, block
+        self.U = synth.gauge_field(dims, eps, seed)
+        self.op = oracle.Operator(dims, self.U, kappa, csw, bc_t)
+        self.field = dfl.Field(dims, block, kappa, csw, self.U, bc_t)
+        self._q = {}
+
+    def qop(self, storage):
+        """Oracle operator on the storage format's quantised links and clover."""
+        if storage not in self._q:
+            lk, ck = quant.STORAGE_KIND[storage], quant.CLOVER_KIND[storage]
+            q = oracle.Operator(self.dims, quant.quantise_links(self.U, lk), self.op.kappa, self.op.csw, self.op.bc_t,
+                                Am=quant.quantise_clover(self.op.Am, ck))
+            q.Ainv = quant.quantise_clover(self.op.Ainv, ck)
+            self._q[storage] = q
+        return self._q[storage]
+
+
+_cases = {}
+
+
+def case(*key):
+    if key not in _cases:
+        _cases[key] = Case(*key)
+    return _cases[key]
+
+
+SMALL = ((8, 4, 4, 8), (2, 2, 2, 2), 0.3, 0.120, 1.0)
+MID = ((8, 8, 8, 16), (4, 4, 4, 4), 0.4, 0.124, 1.5)
+
+
+@pytest.mark.parametrize("key", [SMALL, MID, SMALL + (1,)])
+def test_dirac_fp64_matches_oracle(key):
+    torch, dfl = _gpu()
+    c = case(*key)
+    x = synth.gaussian_spinor(c.dims, 5, 1001)
+    y = dfl.dirac_apply(c.field, torch.from_numpy(x).cuda(), storage=F64).cpu().numpy()
+    ref = c.op.M(x)
+    for r in range(5):
+        assert rel(y[r], ref[r]) <= 1e-12, r
+
+
+@pytest.mark.parametrize("storage", [F32, F16, BF16])
+@pytest.mark.parametrize("key", [SMALL, MID])
+def test_dirac_reduced_precision_matches_quantised_oracle(key, storage):
+    torch, dfl = _gpu()
+    c = case(*key)
+    x = synth.gaussian_spinor(c.dims, 6, 1002).astype(np.complex64)
+    y = dfl.dirac_apply(c.field, torch.from_numpy(x).cuda(), storage=storage).cpu().numpy()
+    ref = c.qop(storage).M(x.astype(np.complex128))
+    unq = c.op.M(x.astype(np.complex128))
+    for r in range(6):
+        assert rel(y[r], ref[r]) <= 1e-5, (r, rel(y[r], ref[r]))
+    # quantisation error against the unquantised operator: reported, bounded loosely
+    assert rel(y[0], unq[0]) < {F32: 1e-6, F16: 3e-3, BF16: 2e-2}[storage]
+
+
+@pytest.mark.parametrize("key", [SMALL, MID])
+def test_sap_fp64_matches_oracle(key):
+    torch, dfl = _gpu()
+    c = case(*key)
+    eta = synth.gaussian_spinor(c.dims, 3, 1003)
+    sp = dfl.SapParams(ncy=5, nmr=4, storage=F64)
+    psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), sp).cpu().numpy()
+    ref = c.op.sap(eta, c.block, 5, 4)
+    for r in range(3):
+        assert rel(psi[r], ref[r]) <= 1e-12, (r, rel(psi[r], ref[r]))
+
+
+@pytest.mark.parametrize("storage", [F32, F16, BF16])
+def test_sap_reduced_precision_matches_quantised_oracle(storage):
+    torch, dfl = _gpu()
+    c = case(*MID)
+    eta = synth.gaussian_spinor(c.dims, 2, 1004).astype(np.complex64)
+    sp = dfl.SapParams(ncy=5, nmr=4, storage=storage)
+    psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), sp).cpu().numpy()
+    ref = c.qop(storage).sap(eta.astype(np.complex128), c.block, 5, 4)
+    for r in range(2):
+        print("sap storage", storage, "rhs", r, "rel err", rel(psi[r], ref[r]))
+        assert rel(psi[r], ref[r]) <= SAP_TOL, (r, rel(psi[r], ref[r]))
+
+
+@pytest.mark.parametrize("dims,block", [
+    ((16, 8, 8, 8), (8, 4, 4, 4)),      # 4^3 x 8 blocks, 256 threads
+    ((12, 12, 12, 12), (6, 6, 6, 6)),   # 648 sites per parity: ragged workgroup
+    ((16, 16, 16, 16), (8, 8, 8, 8)),   # two sites per thread, global exchange buffers
+    ((4, 4, 4, 4), (2, 2, 2, 2)),       # 8 sites per parity in a 64-wide workgroup
+])
+def test_sap_block_shapes(dims, block):
+    torch, dfl = _gpu()
+    c = case(dims, block, 0.4, 0.124, 1.5)
+    eta = synth.gaussian_spinor(dims, 1, 1005).astype(np.complex64)
+    psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), dfl.SapParams(5, 4, F32)).cpu().numpy()
+    ref = c.qop(F32).sap(eta.astype(np.complex128), block, 5, 4)
+    print("sap block", block, "rel err", rel(psi[0], ref[0]))
+    assert rel(psi[0], ref[0]) <= SAP_TOL
+
+
+def test_sap_point_source_and_single_cycle():
+    """Point source: most blocks see a zero residual (alpha guard); ncy = 1."""
+    torch, dfl = _gpu()
+    c = case(*MID)
+    eta = synth.point_source(c.dims, 123, 7)[None]
+    psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), dfl.SapParams(1, 4, F64)).cpu().numpy()
+    ref = c.op.sap(eta, c.block, 1, 4)
+    assert np.all(np.isfinite(psi))
+    assert rel(psi[0], ref[0]) <= 1e-12
+
+
+def test_geometry_errors_are_reported():
+    torch, dfl = _gpu()
+    U = synth.gauge_field((4, 4, 4, 4), 0.3, 1)
+    with pytest.raises(dfl.DflError) as e:
+        dfl.Field((4, 4, 4, 4), (4, 2, 2, 2), 0.12, 1.0, U)
+    assert e.value.code == -2
+    with pytest.raises(dfl.DflError) as e:
+        dfl.Field((4, 4, 4, 4), (3, 2, 2, 2), 0.12, 1.0, U)
+    assert e.value.code == -2
