@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-mode-averaging solve on one MI355X.
+
+Workload (default): 32^3 x 64 lattice, U = exp(i 0.4 H) from seed 1,
+kappa = 0.124, c_sw = 1.5; source positions x0 + g with g on the grid
+{0,16,32,48} x {0,16}^3 (32 positions, block-checkerboard preserving);
+12 point sources per position solved sloppily (FP16 link/clover storage,
+FP32 SAP and Krylov vectors, relative residual 3e-3) and the 12 sources of
+the first position solved exactly (FP64 outer, residual 1e-10), all with
+SAP (n_cy = 5, n_mr = 4) and block-local deflation.
+
+One step = the whole path on one gauge field: field preparation from links
+already in HBM (site tables, storage copies, clover term and inverse),
+deflation setup, all sloppy and exact solves.  The metric is seconds per
+source position (step time / 32); lower is better.
+
+Also reported: a roofline object for the kernel class that takes the most
+time (HIP events on the launch stream, algorithmic work per launch from the
+library's counters), the oracle's time on the host for a bounded sample
+(scaled to the same work), and a per-phase breakdown.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+WORKLOADS = {
+    # the headline configuration
+    "ama-32c64": dict(dims=(64, 32, 32, 32), eps=0.4, kappa=0.124, csw=1.5, seed=1,
+                      grid=((0, 16, 32, 48), (0, 16), (0, 16), (0, 16))),
+    # small configuration for quick checks
+    "ama-16c32": dict(dims=(32, 16, 16, 16), eps=0.4, kappa=0.124, csw=1.5, seed=1,
+                      grid=((0, 16), (0, 8), (0, 8), (0, 8))),
+}
+
+
+def positions(work, block):
+    dims = work["dims"]
+    x0 = synth.seeded_site(dims, work["seed"])
+    t0, xx0, y0, z0 = (int(v) for v in synth.coords(dims, x0))
+    # every shift is a whole number of blocks with an even number of block
+    # steps for the 4^4, 8x4^3 and 8^4 blocks, so M_SAP is covariant under it
+    out = []
+    for gt in work["grid"][0]:
+        for gx in work["grid"][1]:
+            for gy in work["grid"][2]:
+                for gz in work["grid"][3]:
+                    out.append(((t0 + gt) % dims[0], (xx0 + gx) % dims[1], (y0 + gy) % dims[2], (z0 + gz) % dims[3]))
+    return out
+
+
+def sap_flops_per_site_sweep(block, nmr, first=False):
+    hops = sum(2.0 * (b - 1) / b for b in block)
+    h = 165.0 * hops
+    pair = (0.0 if first else 3792.0) + 504 + (h + 72) + nmr * (2 * h + 1392) + (h + 576)
+    return pair / 2
+
+
+def cpu_baseline(work, block, prof, nsrc, ncy, nmr, threads):
+    """Oracle on the host: one M and one M_SAP application (one right-hand
+    side) on the workload's lattice, scaled by the step's site-applications of
+    the stencil and the Schwarz sweeps (deflation setup, little solves and
+    vector algebra are not counted, so this is a lower bound of the oracle's
+    time)."""
+    import oracle
+    dims = work["dims"]
+    U = synth.gauge_field(dims, work["eps"], work["seed"])
+    op = oracle.Operator(dims, U, work["kappa"], work["csw"], -1)
+    _ = op.Ainv
+    x = synth.gaussian_spinor(dims, 1, 1001)[0]
+    t = time.perf_counter()
+    op.M(x)
+    tM = time.perf_counter() - t
+    t = time.perf_counter()
+    op.sap(x, block, ncy, nmr)
+    tS = time.perf_counter() - t
+    V = synth.volume(dims)
+    per_dirac_site = tM / V
+    per_sap_site_sweep = tS / (V * ncy)
+    est = prof["dirac"]["units"] * per_dirac_site + prof["sap"]["units"] * per_sap_site_sweep
+    return {
+        "value": est / nsrc,
+        "unit": "s/source",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"one M ({tM:.2f} s) and one M_SAP ({tS:.2f} s) application, 1 rhs, {dims} lattice, "
+                   f"scaled by the step's {prof['dirac']['units']:.3g} stencil and {prof['sap']['units']:.3g} "
+                   "Schwarz site-applications; deflation setup, little solves and vector algebra not counted"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ama-32c64", choices=sorted(WORKLOADS))
+    ap.add_argument("--block", default="4,4,4,4")
+    ap.add_argument("--ns", type=int, default=12)
+    ap.add_argument("--ninv", type=int, default=5)
+    ap.add_argument("--no-deflation", action="store_true")
+    ap.add_argument("--sloppy-storage", type=int, default=F16)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--little-maxit", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=4, help="source positions per ama_solve call")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--json-only", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: the solve is measured on a single MI355X; --gpus {args.gpus} "
+              "is not supported (multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1605_00564_amd as dfl
+
+    log = (lambda *a: None) if args.json_only else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    work = WORKLOADS[args.workload]
+    dims = work["dims"]
+    block = tuple(int(b) for b in args.block.split(","))
+    V = synth.volume(dims)
+    pos = positions(work, block)
+    npos = len(pos)
+    exact_flags = [i == 0 for i in range(npos)]
+    log(f"[bench] workload {args.workload} dims {dims} block {block} positions {npos}")
+
+    t = time.perf_counter()
+    U = synth.gauge_field(dims, work["eps"], work["seed"])
+    Ud = torch.from_numpy(U).cuda()
+    del U
+    log(f"[bench] gauge field generated and uploaded in {time.perf_counter() - t:.1f} s")
+
+    sap_sloppy = dfl.SapParams(5, 4, args.sloppy_storage)
+    sap_exact = dfl.SapParams(5, 4, F32)
+    xs = [torch.empty((12, V, 4, 3), dtype=torch.complex64, device="cuda") for _ in range(npos)]
+    xe = [torch.empty((12, V, 4, 3), dtype=torch.complex64, device="cuda")]
+
+    state = {}
+
+    def step():
+        ph = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fld = dfl.Field(dims, block, work["kappa"], work["csw"], Ud)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = None
+        if not args.no_deflation:
+            d = dfl.Deflation(fld, Ns=args.ns, ninv=args.ninv, seed=7, sap=sap_sloppy)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sap_sloppy, dfl=d, little_tol=1e-6,
+                               little_maxit=args.little_maxit)
+        exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap_exact, dfl=d, little_tol=1e-10,
+                              little_maxit=args.little_maxit)
+        infs, infe = [], []
+        for c0 in range(0, npos, args.chunk):
+            c1 = min(npos, c0 + args.chunk)
+            ex = exact_flags[c0:c1]
+            _, _, i_s, i_e = dfl.ama_solve(fld, pos[c0:c1], ex, sloppy, exact, dtype=torch.complex64,
+                                           batch=args.batch, out_sloppy=xs[c0:c1],
+                                           out_exact=xe if any(ex) else [])
+            infs += i_s
+            infe += i_e
+            log(f"[bench]   positions {c0}..{c1 - 1} done at {time.perf_counter() - t2:.1f} s")
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ph.update(field=t1 - t0, deflation=t2 - t1, solves=t3 - t2, total=t3 - t0)
+        state.update(infs=infs, infe=infe, fld=fld, dfl=d)
+        return ph
+
+    for w in range(args.warmup):
+        ph = step()
+        log(f"[bench] warmup {w}: {ph}")
+        state.pop("dfl", None)
+        state.pop("fld", None)
+
+    dfl.prof_reset()
+    dfl.prof_enable(True)
+    torch.cuda.synchronize()
+    phases = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        phases.append(step())
+        log(f"[bench] step {k}: {phases[-1]}")
+        if k + 1 < args.steps:
+            state.pop("dfl", None)
+            state.pop("fld", None)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    dfl.prof_enable(False)
+    prof = dfl.prof_get()
+    ms_per_step = 1000.0 * t_total / args.steps
+    s_per_source = t_total / args.steps / npos
+
+    # dominant kernel class
+    dom = max(prof, key=lambda c: prof[c]["ms"])
+    P = prof[dom]
+    avg_ms = P["ms"] / max(P["launches"], 1)
+    if dom == "sap":
+        per_launch = P["flops"] / max(P["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
+    else:
+        per_launch = P["bytes"] / max(P["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["kernel"] = {"sap": "k_sap_sweep", "dirac": "k_dirac", "blas": "vector algebra"}.get(dom, dom)
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = P["launches"]
+    # stencil figures (the Dirac-operator half of the metric)
+    Pd = prof["dirac"]
+    stencil = None
+    if Pd["launches"]:
+        dms = Pd["ms"] / Pd["launches"]
+        stencil = {"bound": "hbm", "achieved": Pd["bytes"] / Pd["launches"] / (dms * 1e-3) / 1e9,
+                   "peak": PEAK_HBM_GBS, "unit": "GB/s", "gflops": Pd["flops"] / (Pd["ms"] * 1e-3) / 1e9,
+                   "avg_launch_ms": dms, "launches": Pd["launches"]}
+        stencil["frac"] = stencil["achieved"] / PEAK_HBM_GBS
+
+    infs, infe = state["infs"], state["infe"]
+    result = {
+        "metric": "AMA solve s/source at 32^3x64 (mixed precision); Dirac-op HBM GB/s vs peak",
+        "value": s_per_source,
+        "unit": "s/source",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": "x".join(str(d) for d in dims), "block": list(block),
+                   "Ns": 0 if args.no_deflation else args.ns, "positions": npos, "sloppy_rhs": 12 * npos,
+                   "exact_rhs": 12, "sloppy_res": 3e-3, "exact_res": 1e-10,
+                   "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage], "ncy": 5, "nmr": 4},
+        "roofline": roof,
+        "stencil_roofline": stencil,
+        "phases_s": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
+        "kernel_ms": {c: prof[c]["ms"] / args.steps for c in prof},
+        "sloppy_iters": [int(min(i.iters for i in infs)), int(max(i.iters for i in infs))],
+        "sloppy_max_rel_res": float(max(i.rel_res for i in infs)),
+        "exact_iters": [int(min(i.iters for i in infe)), int(max(i.iters for i in infe))],
+        "exact_max_rel_res": float(max(i.rel_res for i in infe)),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        result["cpu_baseline"] = cpu_baseline(work, block, {c: prof[c] for c in prof}, npos * args.steps, 5, 4,
+                                              threads)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,11 @@ const char *qcd_last_error(void);
  * reduced storage types.  Singular clover blocks give QCD_ESINGULAR. */
 int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream_t stream,
                      qcd_field *out);
+/* Same, with the complex128 [V][4][3][3] links already in DEVICE memory
+ * (caller-owned, only read during the call): everything after the links
+ * reach HBM (site tables, packing, clover term, inverse) runs on the GPU. */
+int qcd_field_create_device(const qcd_lattice *lat, const double *links_dev, hipStream_t stream,
+                            qcd_field *out);
 int qcd_field_destroy(qcd_field f);
 
 /* out = M in for nrhs vectors (the Dirac operator of section 2.2).
@@ -213,6 +218,11 @@ int qcd_prof_reset(void);
 /* Total milliseconds and launch count for a class since the last reset
  * (synchronises the recorded events). */
 int qcd_prof_get(int cls, double *ms, long long *launches);
+/* Algorithmic work of the recorded launches of a class: flops, compulsory
+ * HBM bytes and work units (site applications per right-hand side; for the
+ * SAP class one unit is one site visited by one colour sweep).  The per-unit
+ * figures are: stencil 1872 flop; SAP sweep see sap.hip; vector algebra 0. */
+int qcd_prof_get_work(int cls, double *flops, double *bytes, double *units);
 
 #ifdef __cplusplus
 }

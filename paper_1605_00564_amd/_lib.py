@@ -79,6 +79,7 @@ def load():
     L.qcd_strerror.argtypes = [I]
     L.qcd_last_error.restype = C.c_char_p
     L.qcd_field_create.argtypes = [C.POINTER(_Lattice), P, P, C.POINTER(P)]
+    L.qcd_field_create_device.argtypes = [C.POINTER(_Lattice), P, P, C.POINTER(P)]
     L.qcd_field_destroy.argtypes = [P]
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
     L.sap_precond.argtypes = [P, C.POINTER(_Sap), P, P, I, I, P]
@@ -97,6 +98,7 @@ def load():
         ("qcd_prof_enable", [I]),
         ("qcd_prof_reset", []),
         ("qcd_prof_get", [I, C.POINTER(D), C.POINTER(C.c_longlong)]),
+        ("qcd_prof_get_work", [I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     ]:
         if hasattr(L, name):
             getattr(L, name).argtypes = args
@@ -184,19 +186,27 @@ class SolveInfo:
 class Field:
     """Gauge field on the device with its packed links and clover term."""
 
-    def __init__(self, dims, block, kappa, csw, U: np.ndarray, bc_t: int = -1):
+    def __init__(self, dims, block, kappa, csw, U, bc_t: int = -1):
+        """U: complex128 [V, 4, 3, 3] as a host numpy array or a GPU tensor."""
         L = load()
-        _torch()
+        torch = _torch()
         self.dims = tuple(int(d) for d in dims)
         self.block = tuple(int(b) for b in block)
         self.V = int(np.prod(self.dims))
-        U = np.ascontiguousarray(U, dtype=np.complex128)
-        if U.shape != (self.V, 4, 3, 3):
-            raise ValueError("links must be complex128 [V, 4, 3, 3]")
         lat = _Lattice((C.c_int * 4)(*self.dims), (C.c_int * 4)(*self.block), float(kappa), float(csw), int(bc_t))
         h = C.c_void_p()
-        _check(L.qcd_field_create(C.byref(lat), U.ctypes.data_as(C.c_void_p), _stream(), C.byref(h)),
-               "qcd_field_create")
+        if isinstance(U, torch.Tensor):
+            if not (U.is_cuda and U.dtype == torch.complex128 and U.is_contiguous()
+                    and tuple(U.shape) == (self.V, 4, 3, 3)):
+                raise ValueError("device links must be a contiguous complex128 GPU tensor [V, 4, 3, 3]")
+            _check(L.qcd_field_create_device(C.byref(lat), C.c_void_p(U.data_ptr()), _stream(), C.byref(h)),
+                   "qcd_field_create_device")
+        else:
+            U = np.ascontiguousarray(U, dtype=np.complex128)
+            if U.shape != (self.V, 4, 3, 3):
+                raise ValueError("links must be complex128 [V, 4, 3, 3]")
+            _check(L.qcd_field_create(C.byref(lat), U.ctypes.data_as(C.c_void_p), _stream(), C.byref(h)),
+                   "qcd_field_create")
         self.handle = h
         self.kappa, self.csw, self.bc_t = float(kappa), float(csw), int(bc_t)
 
@@ -325,17 +335,24 @@ def gcr_solve(field: Field, b, params: GcrParams = None, x=None):
     return x, [SolveInfo(i.status, i.iters, i.rel_res) for i in info]
 
 
-def ama_solve(field: Field, positions, exact_flags, sloppy: GcrParams, exact: GcrParams, dtype=None, batch=0):
+def ama_solve(field: Field, positions, exact_flags, sloppy: GcrParams, exact: GcrParams, dtype=None, batch=0,
+              out_sloppy=None, out_exact=None):
     """Sloppy solves of the 12 point sources at every position, exact solves
-    at the flagged ones.  Returns (x_sloppy[npos], x_exact[nexact], info_s, info_e)."""
+    at the flagged ones.  Returns (x_sloppy[npos], x_exact[nexact], info_s, info_e).
+    Output tensors ([12, V, 4, 3] each) may be passed in to avoid allocation."""
     torch = _torch()
     dtype = dtype or torch.complex64
     npos = len(positions)
     pos = (C.c_int * (4 * npos))(*[int(v) for p in positions for v in p])
     ex = (C.c_ubyte * npos)(*[1 if e else 0 for e in exact_flags])
     nex = sum(1 for e in exact_flags if e)
-    xs = [torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(npos)]
-    xe = [torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(nex)]
+    xs = out_sloppy if out_sloppy is not None else [
+        torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(npos)]
+    xe = out_exact if out_exact is not None else [
+        torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(nex)]
+    for t in list(xs) + list(xe):
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != 12 * field.V * 12:
+            raise ValueError("output tensors must be contiguous [12, V, 4, 3] of the io dtype")
     ps = (C.c_void_p * max(npos, 1))(*[t.data_ptr() for t in xs])
     pe = (C.c_void_p * max(nex, 1))(*[t.data_ptr() for t in xe])
     a = _Ama(npos, C.cast(pos, C.POINTER(C.c_int)), C.cast(ex, C.POINTER(C.c_ubyte)), sloppy.c(), exact.c(), batch)
@@ -357,11 +374,13 @@ def prof_reset():
 
 
 def prof_get():
-    """{class: (milliseconds, launches)} since the last reset."""
+    """{class: dict(ms, launches, flops, bytes, units)} since the last reset."""
     L = load()
     out = {}
     for i, name in enumerate(PROF_CLASSES):
         ms, n = C.c_double(), C.c_longlong()
+        fl, by, un = C.c_double(), C.c_double(), C.c_double()
         _check(L.qcd_prof_get(i, C.byref(ms), C.byref(n)), "qcd_prof_get")
-        out[name] = (ms.value, n.value)
+        _check(L.qcd_prof_get_work(i, C.byref(fl), C.byref(by), C.byref(un)), "qcd_prof_get_work")
+        out[name] = dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value, units=un.value)
     return out

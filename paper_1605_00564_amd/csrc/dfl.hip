@@ -384,6 +384,26 @@ __global__ void k_block_inverse(const double2 *__restrict__ A, double2 *__restri
     }
 }
 
+// loc[idx] = lexicographic site index inside its block, blex[idx] = lexicographic block
+__global__ void k_block_site_tables(Geom g, const int *__restrict__ lex_of, int *__restrict__ loc,
+                                    int *__restrict__ blex) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.V) return;
+    long r = lex_of[idx];
+    int c[4];
+    for (int m = 3; m >= 0; --m) {
+        c[m] = (int)(r % g.L[m]);
+        r /= g.L[m];
+    }
+    int Bl = 0, l = 0;
+    for (int m = 0; m < 4; ++m) {
+        Bl = Bl * g.nb[m] + c[m] / g.b[m];
+        l = l * g.b[m] + c[m] % g.b[m];
+    }
+    loc[idx] = l;
+    blex[idx] = Bl;
+}
+
 // canonical phi [Nb][Ns][Vb][12] complex128 <-> internal block storage
 __global__ void k_phi_export(const float4 *__restrict__ phi, double2 *__restrict__ out, const int *__restrict__ boff,
                              const int *__restrict__ loc, long Vh, int Vbh, int Ns, int Nb) {
@@ -672,7 +692,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     const int Ns = d->Ns, Nb = d->Nb;
     const long V = g.V;
     // block tables (lexicographic block order)
-    std::vector<int> boff(Nb), bnbr((size_t)Nb * 9), loc(V), blex(V), rank(Nb);
+    std::vector<int> boff(Nb), bnbr((size_t)Nb * 9), rank(Nb);
     {
         int cnt[2] = {0, 0};
         for (int B = 0; B < Nb; ++B) {
@@ -700,23 +720,6 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
                     bnbr[(size_t)B * 9 + 1 + 2 * mu + dir] = k;
                 }
         }
-        for (long i = 0; i < V; ++i) {
-            long r = i;
-            int c[4];
-            for (int m = 3; m >= 0; --m) {
-                c[m] = (int)(r % g.L[m]);
-                r /= g.L[m];
-            }
-            int Bl = 0, l = 0;
-            for (int m = 0; m < 4; ++m) {
-                Bl = Bl * g.nb[m] + c[m] / g.b[m];
-                l = l * g.b[m] + c[m] % g.b[m];
-            }
-            const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-            const long idx = p * g.Vh + (long)rank[Bl] * g.Vbh + (l >> 1);
-            loc[idx] = l;
-            blex[idx] = Bl;
-        }
     }
 #define DALLOC(ptr, bytes)                                                                 \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                              \
@@ -737,8 +740,10 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     }
     hipError_t e = hipMemcpyAsync(d->bnbr, bnbr.data(), sizeof(int) * bnbr.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d->boff, boff.data(), sizeof(int) * Nb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d->loc, loc.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d->blex, blex.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        k_block_site_tables<<<nblocks(V, 256), 256, 0, s>>>(g, f->lex_of, d->loc, d->blex);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("deflation upload: ") + hipGetErrorString(e)));
 

@@ -61,17 +61,27 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     const void *U = f->U[LF];
     const void *C = f->clo[CF];
     constexpr int BS = 256;
-    ProfScope ps(PROF_DIRAC, s);
+    // algorithmic work: 1872 flop per site and right-hand side; compulsory
+    // bytes = 4 links + clover per site once, spinor in + out per rhs
+    const double lbytes = LF == LNK_F64 ? 144 : LF == LNK_F32 ? 48 : 24;
+    const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
+    const double sbytes = 2.0 * 24 * sizeof(S);
+    auto work = [&](int n) { return std::make_tuple(1872.0 * V * n, V * (4 * lbytes + cbytes + n * sbytes), 1.0 * V * n); };
     int done = 0;
     constexpr int NR = sizeof(R) == 8 ? 2 : 4;
     if (nrhs >= NR) {
         int ng = nrhs / NR;
+        auto [fl, by, un] = work(ng * NR);
+        ProfScope ps(PROF_DIRAC, s, fl, by, un);
         k_dirac<S, R, LF, CF, NR><<<dim3(nblocks(V, BS), ng), BS, 0, s>>>(in, out, U, C, f->nbr, V, kappa, 0);
         done = ng * NR;
     }
-    if (done < nrhs)
+    if (done < nrhs) {
+        auto [fl, by, un] = work(nrhs - done);
+        ProfScope ps(PROF_DIRAC, s, fl, by, un);
         k_dirac<S, R, LF, CF, 1><<<dim3(nblocks(V, BS), nrhs - done), BS, 0, s>>>(in, out, U, C, f->nbr, V, kappa,
                                                                                   done);
+    }
     DFL_HIP(hipGetLastError());
     return 0;
 }

@@ -46,6 +46,7 @@ static std::vector<ProfRec> g_prof_recs;
 static std::vector<hipEvent_t> g_event_pool;
 static double g_prof_ms[QCD_PROF_CLASSES];
 static long long g_prof_n[QCD_PROF_CLASSES];
+static double g_prof_work[QCD_PROF_CLASSES][3];   // flops, bytes, units
 
 static hipEvent_t take_event() {
     hipEvent_t e = nullptr;
@@ -58,9 +59,12 @@ static hipEvent_t take_event() {
     return e;
 }
 
-ProfScope::ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+ProfScope::ProfScope(int c, hipStream_t st, double flops, double bytes, double units) : cls(c), s(st) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
+    g_prof_work[c][0] += flops;
+    g_prof_work[c][1] += bytes;
+    g_prof_work[c][2] += units;
     e0 = take_event();
     e1 = take_event();
     (void)hipEventRecord(e0, s);
@@ -133,60 +137,58 @@ static int make_geom(const qcd_lattice *lat, Geom &g) {
     return 0;
 }
 
-// internal index of every lexicographic site, and neighbour tables
-static void build_tables(const qcd_lattice *lat, const Geom &g, std::vector<int> &int_of,
-                         std::vector<int> &lex_of, std::vector<int> &nbr) {
-    const long V = g.V;
-    // rank of each block within its colour (lexicographic block order)
-    std::vector<int> rank(g.Nb);
-    int cnt[2] = {0, 0};
-    for (int B = 0; B < g.Nb; ++B) {
-        int r = B, s = 0;
-        for (int m = 3; m >= 0; --m) {
-            s += r % g.nb[m];
-            r /= g.nb[m];
-        }
-        rank[B] = (s & 1) * (g.Nb / 2) + cnt[s & 1]++;
+// Internal index of every lexicographic site.  Because the number of blocks
+// in the fastest direction is even, consecutive blocks (2m, 2m+1) of the
+// lexicographic block order have opposite colours, so the rank of block B
+// among the blocks of its colour is B / 2.
+__device__ inline long internal_index(const Geom &g, long i) {
+    int c[4];
+    long r = i;
+    for (int m = 3; m >= 0; --m) {
+        c[m] = (int)(r % g.L[m]);
+        r /= g.L[m];
     }
-    int_of.assign(V, 0);
-    lex_of.assign(V, 0);
-    for (long i = 0; i < V; ++i) {
-        long r = i;
-        int c[4];
-        for (int m = 3; m >= 0; --m) {
-            c[m] = (int)(r % g.L[m]);
-            r /= g.L[m];
-        }
-        int Bl = 0, l = 0;
-        for (int m = 0; m < 4; ++m) {
-            Bl = Bl * g.nb[m] + c[m] / g.b[m];
-            l = l * g.b[m] + c[m] % g.b[m];
-        }
-        int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-        long idx = p * g.Vh + (long)rank[Bl] * g.Vbh + (l >> 1);
-        int_of[i] = (int)idx;
-        lex_of[idx] = (int)i;
+    int Bl = 0, l = 0, bsum = 0;
+    for (int m = 0; m < 4; ++m) {
+        Bl = Bl * g.nb[m] + c[m] / g.b[m];
+        l = l * g.b[m] + c[m] % g.b[m];
+        bsum += c[m] / g.b[m];
     }
-    nbr.assign(8 * V, 0);
-    for (long i = 0; i < V; ++i) {
-        long r = i;
-        int c[4];
-        for (int m = 3; m >= 0; --m) {
-            c[m] = (int)(r % g.L[m]);
-            r /= g.L[m];
-        }
-        for (int mu = 0; mu < 4; ++mu)
-            for (int d = 0; d < 2; ++d) {
-                int cc[4] = {c[0], c[1], c[2], c[3]};
-                int step = d == 0 ? 1 : -1;
-                bool wrap = (d == 0 && c[mu] == g.L[mu] - 1) || (d == 1 && c[mu] == 0);
-                cc[mu] = (cc[mu] + step + g.L[mu]) % g.L[mu];
-                long j = cc[3] + (long)g.L[3] * (cc[2] + (long)g.L[2] * (cc[1] + (long)g.L[1] * cc[0]));
-                int e = int_of[j];
-                if (mu == 0 && wrap && lat->bc_t == -1) e |= (int)0x80000000u;
-                nbr[(2 * mu + d) * V + int_of[i]] = e;
-            }
+    const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+    const long rank = (long)(bsum & 1) * (g.Nb / 2) + Bl / 2;
+    return p * g.Vh + rank * g.Vbh + (l >> 1);
+}
+
+__global__ void k_site_tables(Geom g, int *__restrict__ int_of, int *__restrict__ lex_of) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    const long idx = internal_index(g, i);
+    int_of[i] = (int)idx;
+    lex_of[idx] = (int)i;
+}
+
+// nbr[2 mu + d][internal x] = internal neighbour, bit 31 set for a hop across
+// the antiperiodic time boundary
+__global__ void k_nbr_table(Geom g, int bc_t, const int *__restrict__ int_of, int *__restrict__ nbr) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int c[4];
+    long r = i;
+    for (int m = 3; m >= 0; --m) {
+        c[m] = (int)(r % g.L[m]);
+        r /= g.L[m];
     }
+    const int xi = int_of[i];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int d = 0; d < 2; ++d) {
+            int cc[4] = {c[0], c[1], c[2], c[3]};
+            const bool wrap = (d == 0 && c[mu] == g.L[mu] - 1) || (d == 1 && c[mu] == 0);
+            cc[mu] = (cc[mu] + (d == 0 ? 1 : -1) + g.L[mu]) % g.L[mu];
+            const long j = cc[3] + (long)g.L[3] * (cc[2] + (long)g.L[2] * (cc[1] + (long)g.L[1] * cc[0]));
+            int e = int_of[j];
+            if (mu == 0 && wrap && bc_t == -1) e |= (int)0x80000000u;
+            nbr[(2 * mu + d) * g.V + xi] = e;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +416,18 @@ int qcd_prof_reset(void) {
     for (int c = 0; c < QCD_PROF_CLASSES; ++c) {
         g_prof_ms[c] = 0;
         g_prof_n[c] = 0;
+        g_prof_work[c][0] = g_prof_work[c][1] = g_prof_work[c][2] = 0;
     }
+    return 0;
+}
+
+int qcd_prof_get_work(int cls, double *flops, double *bytes, double *units) {
+    if (cls < 0 || cls >= QCD_PROF_CLASSES || !flops || !bytes || !units)
+        return set_error(QCD_EINVAL, "bad profiling class");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *flops = g_prof_work[cls][0];
+    *bytes = g_prof_work[cls][1];
+    *units = g_prof_work[cls][2];
     return 0;
 }
 
@@ -427,9 +440,8 @@ int qcd_prof_get(int cls, double *ms, long long *n) {
     return 0;
 }
 
-int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream_t s, qcd_field *out) {
-    if (!lat || !links_host || !out) return set_error(QCD_EINVAL, "null argument to qcd_field_create");
-    *out = nullptr;
+// Build a field handle from complex128 links already in device memory.
+static int field_create_common(const qcd_lattice *lat, const double2 *canon, hipStream_t s, qcd_field *out) {
     if (lat->bc_t != 1 && lat->bc_t != -1) return set_error(QCD_EINVAL, "bc_t must be +1 or -1");
     if (!(lat->kappa > 0) || !std::isfinite(lat->kappa) || !std::isfinite(lat->csw))
         return set_error(QCD_EINVAL, "kappa must be positive and finite, csw finite");
@@ -439,8 +451,6 @@ int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream
     f->lat = *lat;
     f->g = g;
     DFL_HIP(hipGetDevice(&f->device));
-    std::vector<int> int_of, lex_of, nbr;
-    build_tables(lat, g, int_of, lex_of, nbr);
     const long V = g.V, Vh = g.Vh;
     auto fail = [&](int rc) {
         qcd_field_destroy(f);
@@ -465,21 +475,17 @@ int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream
     ALLOC(f->cloinv[CLO_F64], sizeof(double2) * 36 * Vh);
     ALLOC(f->cloinv[CLO_F32], sizeof(float4) * 18 * Vh);
     ALLOC(f->cloinv[CLO_F16], sizeof(h4) * 18 * Vh);
-    double2 *canon = nullptr;
-    ALLOC(canon, sizeof(double2) * 36 * V);
 #undef ALLOC
-    hipError_t e = hipSuccess;
-    e = hipMemcpyAsync(f->nbr, nbr.data(), sizeof(int) * 8 * V, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->int_of, int_of.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->lex_of, lex_of.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(canon, links_host, sizeof(double2) * 36 * V, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
-    if (e != hipSuccess) {
-        (void)hipFree(canon);
-        return fail(set_error(QCD_EHIP, std::string("upload: ") + hipGetErrorString(e)));
+    if (hipHostMalloc((void **)&f->hp, sizeof(double) * 4096) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(QCD_ENOMEM, "pinned host allocation failed"));
     }
+    hipError_t e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
+    if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
     {
         ProfScope ps(PROF_OTHER, s);
+        k_site_tables<<<nblocks(V, 256), 256, 0, s>>>(g, f->int_of, f->lex_of);
+        k_nbr_table<<<nblocks(V, 256), 256, 0, s>>>(g, lat->bc_t, f->int_of, f->nbr);
         k_pack_links<<<nblocks(V, 256), 256, 0, s>>>(canon, f->lex_of, V, (double2 *)f->U[LNK_F64],
                                                     (float4 *)f->U[LNK_F32], (h4 *)f->U[LNK_F16],
                                                     (b4 *)f->U[LNK_BF16]);
@@ -488,15 +494,39 @@ int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream
                                                  (h4 *)f->clo[CLO_F16], (double2 *)f->cloinv[CLO_F64],
                                                  (float4 *)f->cloinv[CLO_F32], (h4 *)f->cloinv[CLO_F16], f->flag);
     }
-    int flag = 0;
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->hp, f->flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(canon);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
-    if (flag) return fail(set_error(QCD_ESINGULAR, "clover block singular on an odd site"));
+    if (*reinterpret_cast<int *>(f->hp)) return fail(set_error(QCD_ESINGULAR, "clover block singular on an odd site"));
     *out = f;
     return 0;
+}
+
+int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream_t s, qcd_field *out) {
+    if (!lat || !links_host || !out) return set_error(QCD_EINVAL, "null argument to qcd_field_create");
+    *out = nullptr;
+    long V = 1;
+    for (int m = 0; m < 4; ++m) V *= lat->dims[m] > 0 ? lat->dims[m] : 0;
+    if (V <= 0) return set_error(QCD_EINVAL, "lattice extents must be positive");
+    double2 *canon = nullptr;
+    if (hipMalloc((void **)&canon, sizeof(double2) * 36 * V) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create");
+    }
+    int rc = 0;
+    hipError_t e = hipMemcpyAsync(canon, links_host, sizeof(double2) * 36 * V, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) rc = set_error(QCD_EHIP, std::string("upload: ") + hipGetErrorString(e));
+    if (rc == 0) rc = field_create_common(lat, canon, s, out);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(canon);
+    return rc;
+}
+
+int qcd_field_create_device(const qcd_lattice *lat, const double *links_dev, hipStream_t s, qcd_field *out) {
+    if (!lat || !links_dev || !out) return set_error(QCD_EINVAL, "null argument to qcd_field_create_device");
+    *out = nullptr;
+    return field_create_common(lat, reinterpret_cast<const double2 *>(links_dev), s, out);
 }
 
 int qcd_field_destroy(qcd_field f) {
@@ -509,6 +539,7 @@ int qcd_field_destroy(qcd_field f) {
     for (auto p : f->clo) (void)hipFree(p);
     for (auto p : f->cloinv) (void)hipFree(p);
     for (auto p : f->buf) (void)hipFree(p);
+    if (f->hp) (void)hipHostFree(f->hp);
     delete f;
     return 0;
 }

@@ -19,8 +19,10 @@ namespace {
 
 int fetch(qcd_field f, const double *dev, size_t count, hipStream_t s, std::vector<double> &host) {
     host.resize(count);
-    DFL_HIP(hipMemcpyAsync(host.data(), dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (count > 4096) return set_error(QCD_EINVAL, "too many right-hand sides in one batch (max 4096)");
+    DFL_HIP(hipMemcpyAsync(f->hp, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
     DFL_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < count; ++i) host[i] = f->hp[i];
     return 0;
 }
 

@@ -31,6 +31,7 @@
 
 #include <cstdint>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dfl.h"
@@ -390,6 +391,7 @@ struct qcd_field_s {
     void *buf[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     size_t buf_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
+    double *hp = nullptr;    // pinned host scratch (4096 doubles)
 };
 
 namespace dfl {
@@ -400,11 +402,14 @@ int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
 
 // Profiling of kernel classes with HIP events.
 enum ProfClass { PROF_DIRAC = 0, PROF_SAP = 1, PROF_DFL = 2, PROF_LITTLE = 3, PROF_BLAS = 4, PROF_OTHER = 5 };
+// One scope per kernel launch of a class: HIP events on the launch stream
+// bracket it, and the launch's algorithmic work (flops, compulsory HBM bytes,
+// work units: site-applications per right-hand side) is accumulated.
 struct ProfScope {
     int cls;
     hipStream_t s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    ProfScope(int cls, hipStream_t s);
+    ProfScope(int cls, hipStream_t s, double flops = 0, double bytes = 0, double units = 0);
     ~ProfScope();
 };
 

@@ -301,13 +301,32 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     }
     const R kappa = (R)f->lat.kappa;
     const long half = (long)nbc * Vbh;
-    ProfScope ps(PROF_SAP, s);
-    // colour 1 sites must start from zero; colour 0 is written by the first sweep
-    k_zero_colour<S><<<dim3(nblocks(2 * half, 256), nrhs), 256, 0, s>>>(psi, g.V, g.Vh, half, half);
+    // Algorithmic work of one sweep per (even, odd) site pair of the swept
+    // colour, with h = 165 flop per hop times the hops that stay inside the
+    // block (sum over mu of 2 (b_mu - 1) / b_mu per site):
+    //   residual 2 x (1872 + 24) (not in the first sweep), s_o = A^-1 rho_o 504,
+    //   rhat_e h + 72, each MinRes step 2h + 1392, back substitution h + 576.
+    // Compulsory bytes: eta, psi in (not first) and out, 4 links and the clover
+    // term per site, the inverse clover per odd site.
+    double hops = 0;
+    for (int m = 0; m < 4; ++m) hops += 2.0 * (g.b[m] - 1) / g.b[m];
+    const double h = 165.0 * hops;
+    const double lbytes = LF == LNK_F64 ? 144 : LF == LNK_F32 ? 48 : 24;
+    const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
+    const double pairs = (double)nbc * Vbh * nrhs;
+    {
+        ProfScope pz(PROF_OTHER, s);
+        // colour 1 sites must start from zero; colour 0 is written by the first sweep
+        k_zero_colour<S><<<dim3(nblocks(2 * half, 256), nrhs), 256, 0, s>>>(psi, g.V, g.Vh, half, half);
+    }
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
             const int first = (cy == 0 && col == 0) ? 1 : 0;
             dim3 grid(nbc, nrhs);
+            const double fl = pairs * ((first ? 0.0 : 3792.0) + 504 + (h + 72) + nmr * (2 * h + 1392) + (h + 576));
+            const double by = pairs * (2 * 24 * sizeof(S) * (first ? 2 : 3)) + (double)nbc * Vbh * 2 *
+                              (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
+            ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
 #define DFL_SAP_LAUNCH(LDSV, KSV, MAXT)                                                                        \
     {                                                                                                          \
         auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT>;                                                \
