@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ 
     for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
 #define DFL_SPLIT(MU, FWD)                                                                   \
     {                                                                                        \
-        const int e = nbr[(2 * MU + (FWD ? 0 : 1)) * V + x];                                 \
+        const int e = nbr_at(nbr, 2 * MU + (FWD ? 0 : 1), V, x);                                 \
         const long y = nb_index(e);                                                          \
         const long by = (y >= Vh ? y - Vh : y) / Vbh;                                        \
         Link<LNK_F64>::load(U, V, MU, FWD ? x : y, w);                                       \
@@ -220,106 +220,229 @@ __device__ inline void rdot<double2>(const float4 &f, const double2 *v, long i0,
     im += (double)f.x * a.y - (double)f.y * a.x + (double)f.z * b.y - (double)f.w * b.x;
 }
 
+// FP64-accumulated restriction, tiles of RL fields x RR right-hand sides per
+// pass over the block (used for FP64 vectors: little-operator assembly and
+// the low-mode corrections of the outer loop).
+constexpr int RL = 4, RR = 4;
 template <class E>
 __global__ void __launch_bounds__(256) k_restrict(const E *__restrict__ v, const float4 *__restrict__ phi,
                                                   const int *__restrict__ boff, double2 *__restrict__ u, long V,
-                                                  long Vh, int Vbh, int Ns, int Nb) {
-    const int B = blockIdx.x, r = blockIdx.y;
+                                                  long Vh, int Vbh, int Ns, int Nb, int n) {
+    const int B = blockIdx.x, r0 = blockIdx.y * RR;
     const long per = 12L * Vbh;
     constexpr int NCH = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4 ? 6 : 12;
-    const E *vr = v + (size_t)r * NCH * V;
     const long bo = boff[B];
-    for (int l = 0; l < Ns; ++l) {
-        const float4 *pl = phi + ((size_t)B * Ns + l) * per;
-        double d[2] = {0, 0}, od[2];
+    for (int l0 = 0; l0 < Ns; l0 += RL) {
+        double d[2 * RL * RR], od[2 * RL * RR];
+#pragma unroll
+        for (int q = 0; q < 2 * RL * RR; ++q) d[q] = 0;
         for (long q = threadIdx.x; q < per; q += blockDim.x) {
             const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
             const long site = p * Vh + bo + j;
-            if (NCH == 6)
-                rdot<E>(pl[q], vr, (long)c * V + site, 0, d[0], d[1]);
-            else
-                rdot<E>(pl[q], vr, (long)(2 * c) * V + site, (long)(2 * c + 1) * V + site, d[0], d[1]);
+#pragma unroll
+            for (int a = 0; a < RL; ++a) {
+                if (l0 + a >= Ns) break;
+                const float4 f = phi[((size_t)B * Ns + l0 + a) * per + q];
+#pragma unroll
+                for (int b = 0; b < RR; ++b) {
+                    if (r0 + b >= n) break;
+                    const E *vr = v + (size_t)(r0 + b) * NCH * V;
+                    double &re = d[2 * (a * RR + b)], &im = d[2 * (a * RR + b) + 1];
+                    if (NCH == 6)
+                        rdot<E>(f, vr, (long)c * V + site, 0, re, im);
+                    else
+                        rdot<E>(f, vr, (long)(2 * c) * V + site, (long)(2 * c + 1) * V + site, re, im);
+                }
+            }
         }
-        wg_sum<2>(d, od);
-        if (threadIdx.x == 0) u[((size_t)r * Nb + B) * Ns + l] = make_double2(od[0], od[1]);
+        wg_sum<2 * RL * RR>(d, od);
+        if (threadIdx.x < RL * RR) {
+            const int a = threadIdx.x / RR, b = threadIdx.x % RR;
+            if (l0 + a < Ns && r0 + b < n)
+                u[((size_t)(r0 + b) * Nb + B) * Ns + l0 + a] = make_double2(od[2 * threadIdx.x], od[2 * threadIdx.x + 1]);
+        }
+    }
+}
+
+// FP32 restriction u = Phi^+ v as a real GEMM on the matrix cores
+// (v_mfma_f32_16x16x4f32, FP32 accumulation).  Rows: 16 deflation fields;
+// columns: 8 right-hand sides x (re, im); K: the real components of the
+// block's sites.  With phi = a + ib and v = c + id, conj(phi) v =
+// (ac + bd) + i(ad - bc): column 2r carries (c, d) and column 2r+1 (d, -c)
+// against the row (a, b).  Lane L supplies A[L % 16][L / 16] and B[L / 16][L % 16]
+// and receives D[4 (L / 16) + i][L % 16], i = 0..3.  Each lane loads one
+// float4 (two complex) of phi and of v per four MFMAs; the K order is
+// (element q + L / 16, component i), identical for both operands.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict__ v, const float4 *__restrict__ phi,
+                                                       const int *__restrict__ boff, double2 *__restrict__ u, long V,
+                                                       long Vh, int Vbh, int Ns, int Nb, int n) {
+    __shared__ float red[4][16][17];
+    const int B = blockIdx.x, r0 = blockIdx.y * 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    const int col = lane & 15, rr = col >> 1, which = col & 1;
+    const long per = 12L * Vbh;
+    const long bo = boff[B];
+    const bool rv = r0 + rr < n;
+    const float4 *vr = v + (size_t)(rv ? r0 + rr : 0) * 6 * V;
+    for (int l0 = 0; l0 < Ns; l0 += 16) {
+        const bool lv = l0 + row < Ns;
+        const float4 *pl = phi + ((size_t)B * Ns + (lv ? l0 + row : 0)) * per;
+        f4v acc = {0.f, 0.f, 0.f, 0.f};
+        // each wave takes every fourth group of four float4 elements
+        for (long q0 = (long)wave * 4; q0 < per; q0 += 16) {
+            const long q = q0 + kk;
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (q < per) {
+                if (lv) a = pl[q];
+                if (rv) {
+                    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+                    b = vr[(long)c * V + p * Vh + bo + j];
+                }
+            }
+            // B operand per component: column (c, d) for which = 0, (d, -c) for which = 1
+            const float b0 = which ? b.y : b.x, b1 = which ? -b.x : b.y;
+            const float b2 = which ? b.w : b.z, b3 = which ? -b.z : b.w;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b2, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b3, acc, 0, 0, 0);
+        }
+        for (int i = 0; i < 4; ++i) red[wave][4 * kk + i][col] = acc[i];
+        __syncthreads();
+        if (threadIdx.x < 128) {
+            const int orow = threadIdx.x >> 3, orr = threadIdx.x & 7;
+            if (l0 + orow < Ns && r0 + orr < n) {
+                double re = 0, im = 0;
+                for (int w = 0; w < 4; ++w) {
+                    re += red[w][orow][2 * orr];
+                    im += red[w][orow][2 * orr + 1];
+                }
+                u[((size_t)(r0 + orr) * Nb + B) * Ns + l0 + orow] = make_double2(re, im);
+            }
+        }
+        __syncthreads();
     }
 }
 
 // v_r (op)= sum_l phi_{B,l} c[r][B][l]; MODE 0: v = .., 1: v -= .., 2: v += ..
+// Each thread owns one float4 element (two complex) of a block and PR
+// right-hand sides, so phi is read once per PR vectors; the coefficients of
+// a block are uniform across the workgroup.
+constexpr int PR = 8;
 template <class E, int MODE>
 __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4 *__restrict__ phi,
                                                  const int *__restrict__ boff, const double2 *__restrict__ cf,
-                                                 long V, long Vh, int Vbh, int Ns, int Nb) {
+                                                 long V, long Vh, int Vbh, int Ns, int Nb, int n) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long per = 12L * Vbh;
     if (t >= (long)Nb * per) return;
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * PR;
+    const int nr = min(PR, n - r0);
     const int B = (int)(t / per);
     const long q = t % per;
     const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
     const long site = p * Vh + boff[B] + j;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-    const double2 *cc = cf + ((size_t)r * Nb + B) * Ns;
+    double ar[PR], ai[PR], br[PR], bi[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) ar[k] = ai[k] = br[k] = bi[k] = 0;
     for (int l = 0; l < Ns; ++l) {
         const float4 f = phi[((size_t)B * Ns + l) * per + q];
-        const double2 k = cc[l];
-        ar += f.x * k.x - f.y * k.y;
-        ai += f.x * k.y + f.y * k.x;
-        br += f.z * k.x - f.w * k.y;
-        bi += f.z * k.y + f.w * k.x;
+#pragma unroll
+        for (int k = 0; k < PR; ++k)
+            if (k < nr) {
+                const double2 w = cf[((size_t)(r0 + k) * Nb + B) * Ns + l];
+                ar[k] += f.x * w.x - f.y * w.y;
+                ai[k] += f.x * w.y + f.y * w.x;
+                br[k] += f.z * w.x - f.w * w.y;
+                bi[k] += f.z * w.y + f.w * w.x;
+            }
     }
     constexpr bool F32V = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4;
-    if constexpr (F32V) {
-        float4 *dst = reinterpret_cast<float4 *>(v) + (size_t)r * 6 * V + (size_t)c * V + site;
-        float4 o = MODE == 0 ? make_float4(0, 0, 0, 0) : *dst;
-        const float sg = MODE == 1 ? -1.f : 1.f;
-        *dst = make_float4(o.x + sg * (float)ar, o.y + sg * (float)ai, o.z + sg * (float)br, o.w + sg * (float)bi);
-    } else {
-        double2 *d0 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c) * V + site;
-        double2 *d1 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c + 1) * V + site;
-        double2 o0 = MODE == 0 ? make_double2(0, 0) : *d0, o1 = MODE == 0 ? make_double2(0, 0) : *d1;
-        const double sg = MODE == 1 ? -1.0 : 1.0;
-        *d0 = make_double2(o0.x + sg * ar, o0.y + sg * ai);
-        *d1 = make_double2(o1.x + sg * br, o1.y + sg * bi);
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+        if (k >= nr) break;
+        const int r = r0 + k;
+        if constexpr (F32V) {
+            float4 *dst = reinterpret_cast<float4 *>(v) + (size_t)r * 6 * V + (size_t)c * V + site;
+            float4 o = MODE == 0 ? make_float4(0, 0, 0, 0) : *dst;
+            const float sg = MODE == 1 ? -1.f : 1.f;
+            *dst = make_float4(o.x + sg * (float)ar[k], o.y + sg * (float)ai[k], o.z + sg * (float)br[k],
+                               o.w + sg * (float)bi[k]);
+        } else {
+            double2 *d0 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c) * V + site;
+            double2 *d1 = reinterpret_cast<double2 *>(v) + (size_t)r * 12 * V + (size_t)(2 * c + 1) * V + site;
+            double2 o0 = MODE == 0 ? make_double2(0, 0) : *d0, o1 = MODE == 0 ? make_double2(0, 0) : *d1;
+            const double sg = MODE == 1 ? -1.0 : 1.0;
+            *d0 = make_double2(o0.x + sg * ar[k], o0.y + sg * ai[k]);
+            *d1 = make_double2(o1.x + sg * br[k], o1.y + sg * bi[k]);
+        }
     }
 }
 
-// w[r][B][k] = sum_d sum_l A[B][d][k][l] v[r][nbr(B,d)][l]
-__global__ void k_little_apply(const double2 *__restrict__ A, const int *__restrict__ bnbr,
-                               const double2 *__restrict__ v, double2 *__restrict__ w, int Nb, int Ns) {
+// w[r][B][k] = sum_d sum_l A[B][d][k][l] v[r][nbr(B,d)][l].  One thread per
+// (B, k) row and up to LR right-hand sides (grid.y covers the rest), so each
+// row of A is read once per LR vectors.
+constexpr int LR = 8;
+__global__ void __launch_bounds__(128) k_little_apply(const double2 *__restrict__ A, const int *__restrict__ bnbr,
+                                                      const double2 *__restrict__ v, double2 *__restrict__ w,
+                                                      int Nb, int Ns, int n) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)Nb * Ns) return;
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * LR;
+    const int nr = min(LR, n - r0);
     const int B = (int)(t / Ns), k = (int)(t % Ns);
-    double sr = 0, si = 0;
+    const size_t N = (size_t)Nb * Ns;
+    double sr[LR], si[LR];
+#pragma unroll
+    for (int q = 0; q < LR; ++q) sr[q] = si[q] = 0;
     for (int d = 0; d < 9; ++d) {
         const double2 *a = A + (((size_t)B * 9 + d) * Ns + k) * Ns;
-        const double2 *x = v + ((size_t)r * Nb + bnbr[B * 9 + d]) * Ns;
+        const double2 *x = v + (size_t)r0 * N + (size_t)bnbr[B * 9 + d] * Ns;
         for (int l = 0; l < Ns; ++l) {
-            const double2 aa = a[l], xx = x[l];
-            sr += aa.x * xx.x - aa.y * xx.y;
-            si += aa.x * xx.y + aa.y * xx.x;
+            const double2 aa = a[l];
+#pragma unroll
+            for (int q = 0; q < LR; ++q)
+                if (q < nr) {
+                    const double2 xx = x[q * N + l];
+                    sr[q] += aa.x * xx.x - aa.y * xx.y;
+                    si[q] += aa.x * xx.y + aa.y * xx.x;
+                }
         }
     }
-    w[(size_t)r * Nb * Ns + t] = make_double2(sr, si);
+#pragma unroll
+    for (int q = 0; q < LR; ++q)
+        if (q < nr) w[(size_t)(r0 + q) * N + t] = make_double2(sr[q], si[q]);
 }
 
 // z[r][B] = Dinv[B] v[r][B]
-__global__ void k_little_jacobi(const double2 *__restrict__ Dinv, const double2 *__restrict__ v,
-                                double2 *__restrict__ z, int Nb, int Ns) {
+__global__ void __launch_bounds__(128) k_little_jacobi(const double2 *__restrict__ Dinv, const double2 *__restrict__ v,
+                                                       double2 *__restrict__ z, int Nb, int Ns, int n) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)Nb * Ns) return;
-    const int r = blockIdx.y;
+    const int r0 = blockIdx.y * LR;
+    const int nr = min(LR, n - r0);
     const int B = (int)(t / Ns), k = (int)(t % Ns);
+    const size_t N = (size_t)Nb * Ns;
     const double2 *a = Dinv + ((size_t)B * Ns + k) * Ns;
-    const double2 *x = v + ((size_t)r * Nb + B) * Ns;
-    double sr = 0, si = 0;
+    const double2 *x = v + (size_t)r0 * N + (size_t)B * Ns;
+    double sr[LR], si[LR];
+#pragma unroll
+    for (int q = 0; q < LR; ++q) sr[q] = si[q] = 0;
     for (int l = 0; l < Ns; ++l) {
-        const double2 aa = a[l], xx = x[l];
-        sr += aa.x * xx.x - aa.y * xx.y;
-        si += aa.x * xx.y + aa.y * xx.x;
+        const double2 aa = a[l];
+#pragma unroll
+        for (int q = 0; q < LR; ++q)
+            if (q < nr) {
+                const double2 xx = x[q * N + l];
+                sr[q] += aa.x * xx.x - aa.y * xx.y;
+                si[q] += aa.x * xx.y + aa.y * xx.x;
+            }
     }
-    z[(size_t)r * Nb * Ns + t] = make_double2(sr, si);
+#pragma unroll
+    for (int q = 0; q < LR; ++q)
+        if (q < nr) z[(size_t)(r0 + q) * N + t] = make_double2(sr[q], si[q]);
 }
 
 // Dinv[B] = A[B][0]^{-1}: Gauss-Jordan with partial pivoting, one thread per
@@ -465,11 +588,27 @@ int dfl_work(qcd_dfl d, size_t bytes, void **p) {
     return 0;
 }
 
+// algorithmic work of Phi^+ v or Phi c: 8 flop per complex multiply-add,
+// Ns x 12 V of them per rhs; bytes: phi once per call plus the vectors
+inline void dfl_work_counts(qcd_dfl d, int n, size_t vbytes_site, double &fl, double &by) {
+    const double V = (double)d->f->g.V;
+    fl = 8.0 * d->Ns * 12.0 * V * n;
+    by = 8.0 * d->Ns * 12.0 * V + (double)vbytes_site * V * n;
+}
+
 template <class E>
 int restrict_v(qcd_dfl d, const E *v, double2 *u, int n, hipStream_t s) {
     const Geom &g = d->f->g;
-    ProfScope ps(PROF_DFL, s);
-    k_restrict<E><<<dim3(d->Nb, n), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns, d->Nb);
+    constexpr bool F32V = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4;
+    double fl, by;
+    dfl_work_counts(d, n, F32V ? 96 : 192, fl, by);
+    ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
+    if constexpr (F32V)
+        k_restrict_mfma<<<dim3(d->Nb, (n + 7) / 8), 256, 0, s>>>(reinterpret_cast<const float4 *>(v), d->phi, d->boff,
+                                                                  u, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n);
+    else
+        k_restrict<E><<<dim3(d->Nb, (n + RR - 1) / RR), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns,
+                                                                      d->Nb, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -477,26 +616,31 @@ int restrict_v(qcd_dfl d, const E *v, double2 *u, int n, hipStream_t s) {
 template <class E, int MODE>
 int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
     const Geom &g = d->f->g;
-    ProfScope ps(PROF_DFL, s);
+    constexpr bool F32V = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4;
+    double fl, by;
+    dfl_work_counts(d, n, (F32V ? 96 : 192) * (MODE == 0 ? 1 : 2), fl, by);
+    ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
     const long tot = (long)d->Nb * 12 * g.Vbh;
-    k_prolong<E, MODE><<<dim3(nblocks(tot, 256), n), 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns,
-                                                                   d->Nb);
+    k_prolong<E, MODE><<<dim3(nblocks(tot, 256), (n + PR - 1) / PR), 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh,
+                                                                                   g.Vbh, d->Ns, d->Nb, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
 
 int little_apply_dev(qcd_dfl d, const double2 *v, double2 *w, int n, hipStream_t s) {
-    ProfScope ps(PROF_LITTLE, s);
     const long N = (long)d->Nb * d->Ns;
-    k_little_apply<<<dim3(nblocks(N, 128), n), 128, 0, s>>>(d->A, d->bnbr, v, w, d->Nb, d->Ns);
+    // 9 Ns^2 complex multiply-adds per block row and rhs; A read once per LR rhs
+    ProfScope ps(PROF_LITTLE, s, 8.0 * 9 * d->Ns * N * n,
+                 16.0 * (9.0 * d->Ns * N * ((n + LR - 1) / LR) + 2.0 * N * n), (double)N * n);
+    k_little_apply<<<dim3(nblocks(N, 128), (n + LR - 1) / LR), 128, 0, s>>>(d->A, d->bnbr, v, w, d->Nb, d->Ns, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
 
 int little_jacobi_dev(qcd_dfl d, const double2 *v, double2 *z, int n, hipStream_t s) {
-    ProfScope ps(PROF_LITTLE, s);
     const long N = (long)d->Nb * d->Ns;
-    k_little_jacobi<<<dim3(nblocks(N, 128), n), 128, 0, s>>>(d->Dinv, v, z, d->Nb, d->Ns);
+    ProfScope ps(PROF_LITTLE, s, 8.0 * d->Ns * N * n, 16.0 * ((double)d->Ns * N + 2.0 * N * n), (double)N * n);
+    k_little_jacobi<<<dim3(nblocks(N, 128), (n + LR - 1) / LR), 128, 0, s>>>(d->Dinv, v, z, d->Nb, d->Ns, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -837,20 +981,29 @@ int little_dirac_solve(qcd_dfl d, const void *v, void *w, int nrhs, double tol, 
 
 int deflation_restrict(qcd_dfl d, const void *v, void *u, int nrhs, qcd_prec io, hipStream_t s) {
     if (!d || !v || !u || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to deflation_restrict");
-    const size_t nb = spinor_bytes(QCD_F64, d->f->g.V) * nrhs;
+    // FP32 io takes the FP32 path of the solver (matrix-core GEMM, FP32
+    // accumulation); FP64 io the FP64-accumulated one
+    const qcd_prec vec = io == QCD_F32 ? QCD_F32 : QCD_F64;
+    const size_t nb = spinor_bytes(vec, d->f->g.V) * nrhs;
     void *ws;
     DFL_TRY(field_buffer(d->f, BUF_APPLY, nb, &ws));
-    DFL_TRY(pack_spinor(d->f, v, io, ws, QCD_F64, nrhs, s));
+    DFL_TRY(pack_spinor(d->f, v, io, ws, vec, nrhs, s));
+    if (vec == QCD_F32)
+        return restrict_v<float4>(d, static_cast<const float4 *>(ws), static_cast<double2 *>(u), nrhs, s);
     return restrict_v<double2>(d, static_cast<const double2 *>(ws), static_cast<double2 *>(u), nrhs, s);
 }
 
 int deflation_prolong(qcd_dfl d, const void *u, void *v, int nrhs, qcd_prec io, hipStream_t s) {
     if (!d || !v || !u || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to deflation_prolong");
-    const size_t nb = spinor_bytes(QCD_F64, d->f->g.V) * nrhs;
+    const qcd_prec vec = io == QCD_F32 ? QCD_F32 : QCD_F64;
+    const size_t nb = spinor_bytes(vec, d->f->g.V) * nrhs;
     void *ws;
     DFL_TRY(field_buffer(d->f, BUF_APPLY, nb, &ws));
-    DFL_TRY((prolong_v<double2, 0>(d, static_cast<double2 *>(ws), static_cast<const double2 *>(u), nrhs, s)));
-    return unpack_spinor(d->f, ws, QCD_F64, v, io, nrhs, s);
+    if (vec == QCD_F32)
+        DFL_TRY((prolong_v<float4, 0>(d, static_cast<float4 *>(ws), static_cast<const double2 *>(u), nrhs, s)));
+    else
+        DFL_TRY((prolong_v<double2, 0>(d, static_cast<double2 *>(ws), static_cast<const double2 *>(u), nrhs, s)));
+    return unpack_spinor(d->f, ws, vec, v, io, nrhs, s);
 }
 
 }  // extern "C"

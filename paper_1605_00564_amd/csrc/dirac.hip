@@ -23,14 +23,14 @@ __global__ void __launch_bounds__(256) k_dirac(const void *__restrict__ in, void
     cx<R> w[9], p[12];
 #define DFL_HOP_MU(MU)                                                        \
     {                                                                         \
-        const int ef = nbr[(2 * MU) * V + x];                                 \
+        const int ef = nbr_at(nbr, 2 * MU, V, x);                                 \
         const long yf = nb_index(ef);                                         \
         Link<LF>::load(U, V, MU, x, w);                                       \
         _Pragma("unroll") for (int r = 0; r < NR; ++r) {                      \
             Spin<S>::load(inb + r * fs, V, yf, p);                            \
             hop<R, MU, true>(w, p, nb_sign<R>(ef), acc[r]);                   \
         }                                                                     \
-        const int eb = nbr[(2 * MU + 1) * V + x];                             \
+        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);                             \
         const long yb = nb_index(eb);                                         \
         Link<LF>::load(U, V, MU, yb, w);                                      \
         _Pragma("unroll") for (int r = 0; r < NR; ++r) {                      \

@@ -462,6 +462,7 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         return fail(set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create"));     \
     }
     ALLOC(f->nbr, sizeof(int) * 8 * V);
+    ALLOC(f->lnbr, sizeof(short) * 16 * g.Vbh);
     ALLOC(f->int_of, sizeof(int) * V);
     ALLOC(f->lex_of, sizeof(int) * V);
     ALLOC(f->flag, sizeof(int));
@@ -480,7 +481,29 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         (void)hipGetLastError();
         return fail(set_error(QCD_ENOMEM, "pinned host allocation failed"));
     }
-    hipError_t e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
+    // in-block neighbour table of the block shape (local lexicographic index l,
+    // parity of l's coordinates, j = l >> 1)
+    std::vector<short> lnb((size_t)16 * g.Vbh, -1);
+    for (int l = 0; l < g.Vb; ++l) {
+        int c[4], r = l;
+        for (int m = 3; m >= 0; --m) {
+            c[m] = r % g.b[m];
+            r /= g.b[m];
+        }
+        const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int d = 0; d < 2; ++d) {
+                int cc[4] = {c[0], c[1], c[2], c[3]};
+                cc[mu] += d == 0 ? 1 : -1;
+                if (cc[mu] < 0 || cc[mu] >= g.b[mu]) continue;
+                int l2 = 0;
+                for (int m = 0; m < 4; ++m) l2 = l2 * g.b[m] + cc[m];
+                lnb[((size_t)p * g.Vbh + (l >> 1)) * 8 + 2 * mu + d] = (short)(l2 >> 1);
+            }
+    }
+    if (g.Vbh > 32767) return fail(set_error(QCD_EINVAL, "Schwarz block too large"));
+    hipError_t e = hipMemcpyAsync(f->lnbr, lnb.data(), sizeof(short) * lnb.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
     {
         ProfScope ps(PROF_OTHER, s);
@@ -532,6 +555,7 @@ int qcd_field_create_device(const qcd_lattice *lat, const double *links_dev, hip
 int qcd_field_destroy(qcd_field f) {
     if (!f) return 0;
     (void)hipFree(f->nbr);
+    (void)hipFree(f->lnbr);
     (void)hipFree(f->int_of);
     (void)hipFree(f->lex_of);
     (void)hipFree(f->flag);

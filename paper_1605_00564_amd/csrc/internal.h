@@ -101,6 +101,50 @@ struct alignas(16) h8 { __half v[8]; };       // 4 complex in FP16
 enum LinkFmt { LNK_F64 = 0, LNK_F32 = 1, LNK_F16 = 2, LNK_BF16 = 3 };
 enum CloFmt { CLO_F64 = 0, CLO_F32 = 1, CLO_F16 = 2 };
 
+// Device-memory tables are read and written through buffer instructions:
+// the descriptor (base address) is uniform and lives in scalar registers,
+// the chunk offset is a scalar offset and the site is a 32-bit per-lane
+// offset, so all chunks of one site share a single VGPR address.  Every
+// base handed to these helpers is within 4 GiB of the chunks it addresses
+// (one right-hand side of a spinor field, one direction of the links, one
+// chirality half of the clover table).
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t mkrsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)0xFFFFFFFFu, 0x00020000);
+}
+template <class T>
+__device__ inline T bld(__amdgpu_buffer_rsrc_t r, unsigned soff, unsigned voff) {
+    if constexpr (sizeof(T) == 16) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    } else if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    } else {
+        static_assert(sizeof(T) == 4, "buffer element size");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    }
+}
+template <class T>
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, unsigned soff, unsigned voff, const T &v) {
+    if constexpr (sizeof(T) == 16) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, (int)voff, (int)soff, 0);
+    } else if constexpr (sizeof(T) == 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
+    } else {
+        static_assert(sizeof(T) == 4, "buffer element size");
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    }
+}
+// element idx of chunk `chunk` of a [chunk][n] table at base
+template <class T>
+__device__ inline T ld(const void *base, size_t chunk, size_t n, unsigned idx) {
+    return bld<T>(mkrsrc(base), (unsigned)(chunk * n * sizeof(T)), idx * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ inline void st(void *base, size_t chunk, size_t n, unsigned idx, const T &v) {
+    bst<T>(mkrsrc(base), (unsigned)(chunk * n * sizeof(T)), idx * (unsigned)sizeof(T), v);
+}
+
 // Spinor storage traits.
 template <class S>
 struct Spin;
@@ -108,41 +152,38 @@ template <>
 struct Spin<double> {
     static constexpr int NCH = 12;
     template <class R>
-    __device__ static inline void load(const void *base, long V, long idx, cx<R> v[12]) {
-        const double2 *p = static_cast<const double2 *>(base);
+    __device__ static inline void load(const void *base, long V, unsigned idx, cx<R> v[12]) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            double2 t = p[k * V + idx];
+            const double2 t = ld<double2>(base, k, V, idx);
             v[k] = {R(t.x), R(t.y)};
         }
     }
     template <class R>
-    __device__ static inline void store(void *base, long V, long idx, const cx<R> v[12]) {
-        double2 *p = static_cast<double2 *>(base);
+    __device__ static inline void store(void *base, long V, unsigned idx, const cx<R> v[12]) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) p[k * V + idx] = make_double2(double(v[k].re), double(v[k].im));
+        for (int k = 0; k < 12; ++k) st<double2>(base, k, V, idx, make_double2(double(v[k].re), double(v[k].im)));
     }
 };
 template <>
 struct Spin<float> {
     static constexpr int NCH = 6;
     template <class R>
-    __device__ static inline void load(const void *base, long V, long idx, cx<R> v[12]) {
-        const float4 *p = static_cast<const float4 *>(base);
+    __device__ static inline void load(const void *base, long V, unsigned idx, cx<R> v[12]) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            float4 t = p[c * V + idx];
+            const float4 t = ld<float4>(base, c, V, idx);
             v[2 * c] = {R(t.x), R(t.y)};
             v[2 * c + 1] = {R(t.z), R(t.w)};
         }
     }
     template <class R>
-    __device__ static inline void store(void *base, long V, long idx, const cx<R> v[12]) {
-        float4 *p = static_cast<float4 *>(base);
+    __device__ static inline void store(void *base, long V, unsigned idx, const cx<R> v[12]) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
-            p[c * V + idx] = make_float4(float(v[2 * c].re), float(v[2 * c].im), float(v[2 * c + 1].re),
-                                         float(v[2 * c + 1].im));
+            st<float4>(base, c, V, idx,
+                       make_float4(float(v[2 * c].re), float(v[2 * c].im), float(v[2 * c + 1].re),
+                                   float(v[2 * c + 1].im)));
     }
 };
 
@@ -155,11 +196,10 @@ struct Link;
 template <>
 struct Link<LNK_F64> {
     template <class R>
-    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
-        const double2 *p = static_cast<const double2 *>(base) + (long)mu * 9 * V;
+    __device__ static inline void load(const void *base, long V, int mu, unsigned idx, cx<R> w[9]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 t = p[k * V + idx];
+            const double2 t = ld<double2>(static_cast<const double2 *>(base) + (size_t)mu * 9 * V, k, V, idx);
             w[k] = {R(t.x), R(t.y)};
         }
     }
@@ -174,11 +214,10 @@ __device__ inline void rebuild_row2(cx<R> w[9]) {
 template <>
 struct Link<LNK_F32> {
     template <class R>
-    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
-        const float4 *p = static_cast<const float4 *>(base) + (long)mu * 3 * V;
+    __device__ static inline void load(const void *base, long V, int mu, unsigned idx, cx<R> w[9]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float4 t = p[c * V + idx];
+            const float4 t = ld<float4>(static_cast<const float4 *>(base) + (size_t)mu * 3 * V, c, V, idx);
             w[2 * c] = {R(t.x), R(t.y)};
             w[2 * c + 1] = {R(t.z), R(t.w)};
         }
@@ -188,11 +227,10 @@ struct Link<LNK_F32> {
 template <>
 struct Link<LNK_F16> {
     template <class R>
-    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
-        const h4 *p = static_cast<const h4 *>(base) + (long)mu * 3 * V;
+    __device__ static inline void load(const void *base, long V, int mu, unsigned idx, cx<R> w[9]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            h4 t = p[c * V + idx];
+            const h4 t = ld<h4>(static_cast<const h4 *>(base) + (size_t)mu * 3 * V, c, V, idx);
             w[2 * c] = {R(__half2float(t.v[0])), R(__half2float(t.v[1]))};
             w[2 * c + 1] = {R(__half2float(t.v[2])), R(__half2float(t.v[3]))};
         }
@@ -202,11 +240,10 @@ struct Link<LNK_F16> {
 template <>
 struct Link<LNK_BF16> {
     template <class R>
-    __device__ static inline void load(const void *base, long V, int mu, long idx, cx<R> w[9]) {
-        const b4 *p = static_cast<const b4 *>(base) + (long)mu * 3 * V;
+    __device__ static inline void load(const void *base, long V, int mu, unsigned idx, cx<R> w[9]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            b4 t = p[c * V + idx];
+            const b4 t = ld<b4>(static_cast<const b4 *>(base) + (size_t)mu * 3 * V, c, V, idx);
             w[2 * c] = {R(__bfloat162float(t.v[0])), R(__bfloat162float(t.v[1]))};
             w[2 * c + 1] = {R(__bfloat162float(t.v[2])), R(__bfloat162float(t.v[3]))};
         }
@@ -220,11 +257,10 @@ struct Clo;
 template <>
 struct Clo<CLO_F64> {
     template <class R>
-    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
-        const double2 *p = static_cast<const double2 *>(base) + (long)h * 18 * n;
+    __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            double2 t = p[k * n + at];
+            const double2 t = ld<double2>(static_cast<const double2 *>(base) + (size_t)h * 18 * n, k, n, at);
             a[2 * k] = R(t.x);
             a[2 * k + 1] = R(t.y);
         }
@@ -233,11 +269,10 @@ struct Clo<CLO_F64> {
 template <>
 struct Clo<CLO_F32> {
     template <class R>
-    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
-        const float4 *p = static_cast<const float4 *>(base) + (long)h * 9 * n;
+    __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float4 t = p[k * n + at];
+            const float4 t = ld<float4>(static_cast<const float4 *>(base) + (size_t)h * 9 * n, k, n, at);
             a[4 * k] = R(t.x);
             a[4 * k + 1] = R(t.y);
             a[4 * k + 2] = R(t.z);
@@ -248,11 +283,10 @@ struct Clo<CLO_F32> {
 template <>
 struct Clo<CLO_F16> {
     template <class R>
-    __device__ static inline void load_half(const void *base, long n, long at, int h, R a[36]) {
-        const h4 *p = static_cast<const h4 *>(base) + (long)h * 9 * n;
+    __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            h4 t = p[k * n + at];
+            const h4 t = ld<h4>(static_cast<const h4 *>(base) + (size_t)h * 9 * n, k, n, at);
 #pragma unroll
             for (int e = 0; e < 4; ++e) a[4 * k + e] = R(__half2float(t.v[e]));
         }
@@ -279,7 +313,7 @@ __device__ inline void herm6_apply(const R *h, const cx<R> v[6], cx<R> out[6]) {
 // out = A v for the clover of site `at` of a table with n entries, read and
 // applied one chirality half at a time.
 template <int CF, class R>
-__device__ inline void clover_apply(const void *clo, long n, long at, const cx<R> v[12], cx<R> out[12]) {
+__device__ inline void clover_apply(const void *clo, long n, unsigned at, const cx<R> v[12], cx<R> out[12]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         R a[36];
@@ -361,8 +395,10 @@ __device__ inline void hop(const cx<R> w[9], const cx<R> psi[12], R sign, cx<R> 
     reconstruct_add<R, MU, S>(g, sign, acc);
 }
 
-// neighbour table entries: bit 31 marks the antiperiodic time-boundary sign
-__device__ inline long nb_index(int e) { return (long)(e & 0x7fffffff); }
+// neighbour table: entry of site x in direction d = 2 mu + (0 fwd | 1 bwd);
+// bit 31 marks the antiperiodic time-boundary sign
+__device__ inline int nbr_at(const int *nbr, int d, long V, unsigned x) { return ld<int>(nbr, d, V, x); }
+__device__ inline unsigned nb_index(int e) { return (unsigned)(e & 0x7fffffff); }
 template <class R>
 __device__ inline R nb_sign(int e) { return e < 0 ? R(-1) : R(1); }
 
@@ -382,6 +418,7 @@ struct qcd_field_s {
     dfl::Geom g;
     int device = 0;
     int *nbr = nullptr;      // [8][V], direction d = 2*mu + (0 fwd | 1 bwd)
+    short *lnbr = nullptr;   // [2 parity][Vbh][8]: in-block neighbour (local j) or -1; same for every block
     int *int_of = nullptr;   // [V] lexicographic -> internal
     int *lex_of = nullptr;   // [V] internal -> lexicographic
     void *U[4] = {nullptr, nullptr, nullptr, nullptr};      // by LinkFmt

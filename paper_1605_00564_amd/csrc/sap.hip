@@ -23,31 +23,35 @@ __device__ inline R wave_sum(R v) {
 }
 
 // acc = sum over hops that stay inside the block (Dirichlet boundary) of the
-// hopping term applied to the exchange buffer buf (opposite parity sites).
-template <class R, int LF>
-__device__ inline void block_hop(const void *U, const int *nbr, long V, long Vh, long x, long boff, int Vbh,
+// hopping term applied to the exchange buffer buf (opposite-parity sites of
+// the block, local index).  Site: local index j of parity ODD in the block at
+// offset boff.  The in-block neighbours come from the block-shape table
+// lnbr (identical for every block); hops inside a block never cross the
+// lattice boundary, so no boundary sign enters.
+template <class R, int LF, bool ODD>
+__device__ inline void block_hop(const void *U, const short *lnbr, long V, long Vh, long boff, int j, int Vbh,
                                  const cx<R> *buf, cx<R> acc[12]) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
     cx<R> w[9], p[12];
-#define DFL_BHOP(MU)                                                                  \
-    {                                                                                 \
-        const int ef = nbr[(2 * MU) * V + x];                                         \
-        long yf = nb_index(ef);                                                       \
-        long lf = (yf >= Vh ? yf - Vh : yf) - boff;                                   \
-        if (lf >= 0 && lf < Vbh) {                                                    \
-            Link<LF>::load(U, V, MU, x, w);                                           \
-            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lf];  \
-            hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);                              \
-        }                                                                             \
-        const int eb = nbr[(2 * MU + 1) * V + x];                                     \
-        long yb = nb_index(eb);                                                       \
-        long lb = (yb >= Vh ? yb - Vh : yb) - boff;                                   \
-        if (lb >= 0 && lb < Vbh) {                                                    \
-            Link<LF>::load(U, V, MU, yb, w);                                          \
-            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lb];  \
-            hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);                             \
-        }                                                                             \
+    const uint4 nb4 = ld<uint4>(lnbr, 0, 0, (unsigned)((ODD ? Vbh : 0) + j));
+    const unsigned nbw[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+    const unsigned x = (unsigned)((ODD ? Vh : 0) + boff + j);
+    const unsigned yoff = (unsigned)((ODD ? 0 : Vh) + boff);
+#define DFL_BHOP(MU)                                                                    \
+    {                                                                                   \
+        const int lf = (short)(nbw[MU] & 0xffffu);                                      \
+        const int lb = (short)(nbw[MU] >> 16);                                          \
+        if (lf >= 0) {                                                                  \
+            Link<LF>::load(U, V, MU, x, w);                                             \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lf];    \
+            hop<R, MU, true>(w, p, R(1), acc);                                          \
+        }                                                                               \
+        if (lb >= 0) {                                                                  \
+            Link<LF>::load(U, V, MU, yoff + (unsigned)lb, w);                           \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) p[k] = buf[k * Vbh + lb];    \
+            hop<R, MU, false>(w, p, R(1), acc);                                         \
+        }                                                                               \
     }
     DFL_BHOP(0)
     DFL_BHOP(1)
@@ -65,11 +69,11 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
 #define DFL_FHOP(MU)                                          \
     {                                                         \
-        const int ef = nbr[(2 * MU) * V + x];                 \
+        const int ef = nbr_at(nbr, 2 * MU, V, x);                 \
         Link<LF>::load(U, V, MU, x, w);                       \
         Spin<S>::load(psi, V, nb_index(ef), p);               \
         hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);          \
-        const int eb = nbr[(2 * MU + 1) * V + x];             \
+        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);             \
         Link<LF>::load(U, V, MU, nb_index(eb), w);            \
         Spin<S>::load(psi, V, nb_index(eb), p);               \
         hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);         \
@@ -88,8 +92,9 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
 template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT>
 __global__ void __launch_bounds__(MAXT)
     k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, const void *__restrict__ U,
-                const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr, long V,
-                long Vh, int Vbh, int nbc, int colour, R kappa, int nmr, int first, cx<R> *gbuf) {
+                const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr,
+                const short *__restrict__ lnbr, long V, long Vh, int Vbh, int nbc, int colour, R kappa, int nmr,
+                int first, cx<R> *gbuf) {
     extern __shared__ unsigned char dsm[];
     __shared__ R red[16][3];
     const int NT = blockDim.x;
@@ -144,7 +149,7 @@ __global__ void __launch_bounds__(MAXT)
         const int j = tid + k * NT;
         if (j < Vbh) {
             cx<R> acc[12], q[12];
-            block_hop<R, LF>(U, nbr, V, Vh, boff + j, boff, Vbh, Tb, acc);
+            block_hop<R, LF, false>(U, lnbr, V, Vh, boff, j, Vbh, Tb, acc);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 Rb[c * Vbh + j] = Rb[c * Vbh + j] + kappa * acc[c];
@@ -171,7 +176,7 @@ __global__ void __launch_bounds__(MAXT)
             const int j = tid + k * NT;
             if (j < Vbh) {
                 cx<R> acc[12], t[12];
-                block_hop<R, LF>(U, nbr, V, Vh, Vh + boff + j, boff, Vbh, Rb, acc);
+                block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
                 clover_apply<CF>(cinv, Vh, boff + j, acc, t);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = t[c];
@@ -189,7 +194,7 @@ __global__ void __launch_bounds__(MAXT)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) r[c] = Rb[c * Vbh + j];
                 clover_apply<CF>(clo, V, boff + j, r, p[k]);
-                block_hop<R, LF>(U, nbr, V, Vh, boff + j, boff, Vbh, Tb, acc);
+                block_hop<R, LF, false>(U, lnbr, V, Vh, boff, j, Vbh, Tb, acc);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     p[k][c] = p[k][c] - k2 * acc[c];
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(MAXT)
         if (j < Vbh) {
             const long xe_i = boff + j, xo_i = Vh + boff + j;
             cx<R> acc[12], t[12], q[12];
-            block_hop<R, LF>(U, nbr, V, Vh, xo_i, boff, Vbh, Rb, acc);
+            block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
             clover_apply<CF>(cinv, Vh, boff + j, acc, t);
             Spin<S>::load(psi, V, xo_i, q);
 #pragma unroll
@@ -333,7 +338,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
         size_t sh = LDSV ? lds : 0;                                                                            \
         if (LDSV && sh > 64 * 1024) (void)hipFuncSetAttribute((const void *)kern,                              \
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
-        kern<<<grid, NT, sh, s>>>(eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, g.V, g.Vh, Vbh, nbc, col, \
+        kern<<<grid, NT, sh, s>>>(eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, g.V, g.Vh, Vbh, nbc, col, \
                                   kappa, nmr, first, gbuf);                                                    \
     }
             if (use_lds) {

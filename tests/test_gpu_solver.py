@@ -198,6 +198,28 @@ def test_restrict_prolong_match_oracle(dfl_given_phi):
         assert rel(pv[r], ref.prolong(c[r])) <= 1e-12
 
 
+@pytest.mark.parametrize("Ns,n", [(8, 10), (20, 3)])
+def test_fp32_restrict_prolong_match_oracle(Ns, n):
+    """FP32 vectors: the restriction runs as a real GEMM on the matrix cores
+    (FP32 accumulation over 12 V_b complex products), the prolongation on the
+    vector units.  Tiles: 16 fields x 8 right-hand sides; Ns = 20 needs two
+    field tiles, n = 10 a partial rhs tile.  Bound: FP32 rounding of a sum of
+    12 V_b = 3072 products, 1e-5 relative."""
+    torch, dfl = _gpu()
+    op, fld = setup(*DFL_KEY)
+    d = dfl.Deflation(fld, Ns=Ns, ninv=1, seed=13, sap=dfl.SapParams(5, 4, F32))
+    phi = d.get_phi().cpu().numpy().reshape(d.Nb, d.Ns, -1)
+    ref = oracle.Deflation(op, fld.block, Ns=Ns, phi=phi)
+    v = synth.gaussian_spinor(fld.dims, n, 2102).astype(np.complex64)
+    u = d.restrict(torch.from_numpy(v).cuda()).cpu().numpy()
+    for r in range(n):
+        assert rel(u[r], ref.restrict(v[r].astype(np.complex128))) <= 1e-5, r
+    c = np.ascontiguousarray(u)
+    pv = d.prolong(torch.from_numpy(c).cuda(), dtype=torch.complex64).cpu().numpy()
+    for r in range(n):
+        assert rel(pv[r], ref.prolong(c[r])) <= 1e-6, r
+
+
 def test_little_solve_residual(dfl_given_phi):
     torch, dfl = _gpu()
     op, fld, d, ref = dfl_given_phi
