@@ -106,8 +106,53 @@ def cpu_baseline(work, block, prof, nsrc, ncy, nmr, threads):
     }
 
 
+def stencil_sweep(lattices, storages, nrhs_list, reps, log):
+    """Dirac-operator GB/s and Gflop/s per storage mode and right-hand-side
+    count (kernel time from HIP events; pack/unpack kernels excluded)."""
+    import torch
+    import paper_1605_00564_amd as dfl
+    rows = []
+    for dims in lattices:
+        U = synth.gauge_field(dims, 0.4, 1)
+        fld = dfl.Field(dims, (4, 4, 4, 4), 0.124, 1.5, torch.from_numpy(U).cuda())
+        del U
+        V = synth.volume(dims)
+        for st in storages:
+            dt = torch.complex128 if st == F64 else torch.complex64
+            for n in nrhs_list:
+                x = torch.randn((n, V, 4, 3), dtype=dt, device="cuda")
+                y = torch.empty_like(x)
+                for _ in range(2):
+                    dfl.dirac_apply(fld, x, storage=st, out=y)
+                torch.cuda.synchronize()
+                dfl.prof_reset()
+                dfl.prof_enable(True)
+                for _ in range(reps):
+                    dfl.dirac_apply(fld, x, storage=st, out=y)
+                torch.cuda.synchronize()
+                dfl.prof_enable(False)
+                P = dfl.prof_get()["dirac"]
+                ms = P["ms"] / reps
+                row = {"lattice": "x".join(map(str, dims)), "storage": ["f64", "f32", "f16", "bf16"][st], "nrhs": n,
+                       "ms": ms, "GB/s": P["bytes"] / (P["ms"] * 1e-3) / 1e9,
+                       "Gflop/s": P["flops"] / (P["ms"] * 1e-3) / 1e9,
+                       "frac_hbm": P["bytes"] / (P["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                rows.append(row)
+                log(json.dumps(row))
+                del x, y
+        fld.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--stencil-sweep", action="store_true",
+                    help="only measure the Dirac stencil over storage modes and rhs counts")
+    ap.add_argument("--sweep-lattices", default="32x16x16x16,64x32x32x32", help="T x X x Y x Z, comma separated")
+    ap.add_argument("--sweep-storage", default="0,1,2,3")
+    ap.add_argument("--sweep-nrhs", default="1,4,12,24")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run five 1 GiB device copies (reference for hardware byte counters)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
@@ -133,6 +178,22 @@ def main():
     import paper_1605_00564_amd as dfl
 
     log = (lambda *a: None) if args.json_only else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.copy_calibration:
+        # a plain device copy of known size, to scale the HBM byte counters
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)    # one elementwise kernel: reads a, writes b
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "copies": 5}), flush=True)
+        return
+    if args.stencil_sweep:
+        lats = [tuple(int(v) for v in s.split("x")) for s in args.sweep_lattices.split(",")]
+        rows = stencil_sweep(lats, [int(v) for v in args.sweep_storage.split(",")],
+                             [int(v) for v in args.sweep_nrhs.split(",")], 10, log)
+        print(json.dumps({"stencil_sweep": rows}), flush=True)
+        return
     work = WORKLOADS[args.workload]
     dims = work["dims"]
     block = tuple(int(b) for b in args.block.split(","))

@@ -5,53 +5,56 @@
 
 namespace dfl {
 
-// One thread per site; NR right-hand sides per thread share every link load.
-template <class S, class R, int LF, int CF, int NR>
-__global__ void __launch_bounds__(256) k_dirac(const void *__restrict__ in, void *__restrict__ out,
-                                               const void *__restrict__ U, const void *__restrict__ clo,
-                                               const int *__restrict__ nbr, long V, R kappa, int rhs0) {
-    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= V) return;
-    const size_t fs = (size_t)Spin<S>::NCH * V * 16;  // bytes per right-hand side
-    const char *inb = static_cast<const char *>(in) + (size_t)(rhs0 + blockIdx.y * NR) * fs;
-    char *outb = static_cast<char *>(out) + (size_t)(rhs0 + blockIdx.y * NR) * fs;
-    cx<R> acc[NR][12];
+// Site mapping: a workgroup owns a tile of `tile` consecutive sites of the
+// even half and the same tile of the odd half (the same Schwarz-block
+// positions), so the opposite-parity neighbours and the backward links a
+// site needs were fetched by the other half of the same workgroup.  RG
+// adjacent lanes share one site, one right-hand side each: their link and
+// clover loads hit the same address inside one wave instruction (fetched
+// once per group) while spinor loads stay coalesced per right-hand side.
+// The clover term is read exactly once per site and group, so its loads are
+// non-temporal and do not evict the reused spinors and links from L2.
+template <class S, class R, int LF, int CF, int RG>
+__global__ void __launch_bounds__(256) k_dirac_rg(const void *__restrict__ in, void *__restrict__ out,
+                                                  const void *__restrict__ U, const void *__restrict__ clo,
+                                                  const int *__restrict__ nbr, long V, R kappa, int nrhs) {
+    unsigned bx, by;
+    xcd_order(bx, by);
+    const int tile = blockDim.x / (2 * RG);
+    const int sub = threadIdx.x % RG;
+    const int sl = threadIdx.x / RG;
+    const int par = sl >= tile ? 1 : 0;
+    const long x = (long)par * (V / 2) + (long)bx * tile + (sl - par * tile);
+    const int r = by * RG + sub;
+    if (r >= nrhs) return;
+    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
+    const char *inb = static_cast<const char *>(in) + (size_t)r * fs;
+    char *outb = static_cast<char *>(out) + (size_t)r * fs;
+    cx<R> acc[12], w[9], p[12];
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[r][k] = {R(0), R(0)};
-    cx<R> w[9], p[12];
-#define DFL_HOP_MU(MU)                                                        \
-    {                                                                         \
-        const int ef = nbr_at(nbr, 2 * MU, V, x);                                 \
-        const long yf = nb_index(ef);                                         \
-        Link<LF>::load(U, V, MU, x, w);                                       \
-        _Pragma("unroll") for (int r = 0; r < NR; ++r) {                      \
-            Spin<S>::load(inb + r * fs, V, yf, p);                            \
-            hop<R, MU, true>(w, p, nb_sign<R>(ef), acc[r]);                   \
-        }                                                                     \
-        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);                             \
-        const long yb = nb_index(eb);                                         \
-        Link<LF>::load(U, V, MU, yb, w);                                      \
-        _Pragma("unroll") for (int r = 0; r < NR; ++r) {                      \
-            Spin<S>::load(inb + r * fs, V, yb, p);                            \
-            hop<R, MU, false>(w, p, nb_sign<R>(eb), acc[r]);                  \
-        }                                                                     \
+    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+#define DFL_HOP_RG(MU)                                     \
+    {                                                      \
+        const int ef = nbr_at(nbr, 2 * MU, V, x);          \
+        Link<LF>::load(U, V, MU, x, w);                    \
+        Spin<S>::load(inb, V, nb_index(ef), p);            \
+        hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);       \
+        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);      \
+        Link<LF>::load(U, V, MU, nb_index(eb), w);         \
+        Spin<S>::load(inb, V, nb_index(eb), p);            \
+        hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);      \
     }
-    DFL_HOP_MU(0)
-    DFL_HOP_MU(1)
-    DFL_HOP_MU(2)
-    DFL_HOP_MU(3)
-#undef DFL_HOP_MU
+    DFL_HOP_RG(0)
+    DFL_HOP_RG(1)
+    DFL_HOP_RG(2)
+    DFL_HOP_RG(3)
+#undef DFL_HOP_RG
+    cx<R> o[12];
+    Spin<S>::load(inb, V, x, p);
+    clover_apply<CF, R, true>(clo, V, x, p, o);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        cx<R> o[12];
-        Spin<S>::load(inb + r * fs, V, x, p);
-        clover_apply<CF>(clo, V, x, p, o);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = o[k] - kappa * acc[r][k];
-        Spin<S>::store(outb + r * fs, V, x, o);
-    }
+    for (int k = 0; k < 12; ++k) o[k] = o[k] - kappa * acc[k];
+    Spin<S>::store(outb, V, x, o);
 }
 
 template <class S, class R, int LF, int CF>
@@ -67,21 +70,25 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
     const double sbytes = 2.0 * 24 * sizeof(S);
     auto work = [&](int n) { return std::make_tuple(1872.0 * V * n, V * (4 * lbytes + cbytes + n * sbytes), 1.0 * V * n); };
-    int done = 0;
-    constexpr int NR = sizeof(R) == 8 ? 2 : 4;
-    if (nrhs >= NR) {
-        int ng = nrhs / NR;
-        auto [fl, by, un] = work(ng * NR);
-        ProfScope ps(PROF_DIRAC, s, fl, by, un);
-        k_dirac<S, R, LF, CF, NR><<<dim3(nblocks(V, BS), ng), BS, 0, s>>>(in, out, U, C, f->nbr, V, kappa, 0);
-        done = ng * NR;
+    // right-hand sides per site group (tuning knob; 0 = automatic)
+    static const int rg_env = [] {
+        const char *e = getenv("DFL_STENCIL_RG");
+        return e ? atoi(e) : 0;
+    }();
+    int rg = rg_env > 0 ? rg_env : (nrhs >= 2 ? 2 : 1);
+    auto [fl, by, un] = work(nrhs);
+    ProfScope ps(PROF_DIRAC, s, fl, by, un);
+    // grid: (V / 2) / tile site tiles x ceil(nrhs / RG) groups; V/2 is a multiple of 128
+#define DFL_RG_LAUNCH(RGV)                                                                            \
+    k_dirac_rg<S, R, LF, CF, RGV><<<dim3((unsigned)(V / 2 / (BS / (2 * RGV))), (nrhs + RGV - 1) / RGV), BS, 0, s>>>( \
+        in, out, U, C, f->nbr, V, kappa, nrhs)
+    switch (rg) {
+        case 2: DFL_RG_LAUNCH(2); break;
+        case 4: DFL_RG_LAUNCH(4); break;
+        case 8: DFL_RG_LAUNCH(8); break;
+        default: DFL_RG_LAUNCH(1);
     }
-    if (done < nrhs) {
-        auto [fl, by, un] = work(nrhs - done);
-        ProfScope ps(PROF_DIRAC, s, fl, by, un);
-        k_dirac<S, R, LF, CF, 1><<<dim3(nblocks(V, BS), nrhs - done), BS, 0, s>>>(in, out, U, C, f->nbr, V, kappa,
-                                                                                  done);
-    }
+#undef DFL_RG_LAUNCH
     DFL_HIP(hipGetLastError());
     return 0;
 }

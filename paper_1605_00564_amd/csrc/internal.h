@@ -140,6 +140,16 @@ template <class T>
 __device__ inline T ld(const void *base, size_t chunk, size_t n, unsigned idx) {
     return bld<T>(mkrsrc(base), (unsigned)(chunk * n * sizeof(T)), idx * (unsigned)sizeof(T));
 }
+// same, marked non-temporal (streamed data read once: keeps L2 for reused data)
+template <class T>
+__device__ inline T ld_nt(const void *base, size_t chunk, size_t n, unsigned idx) {
+    const __amdgpu_buffer_rsrc_t r = mkrsrc(base);
+    const unsigned soff = (unsigned)(chunk * n * sizeof(T)), voff = idx * (unsigned)sizeof(T);
+    if constexpr (sizeof(T) == 16)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 2));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 2));
+}
 template <class T>
 __device__ inline void st(void *base, size_t chunk, size_t n, unsigned idx, const T &v) {
     bst<T>(mkrsrc(base), (unsigned)(chunk * n * sizeof(T)), idx * (unsigned)sizeof(T), v);
@@ -251,16 +261,24 @@ struct Link<LNK_BF16> {
     }
 };
 
-// Clover access: one chirality half (36 reals) of a site's packed clover.
+// Clover access: one chirality half (36 reals) of a site's packed clover;
+// NT marks the loads non-temporal (clover read once per site by the stencil).
+template <class T, bool NT>
+__device__ inline T ldc(const void *base, size_t chunk, size_t n, unsigned idx) {
+    if constexpr (NT)
+        return ld_nt<T>(base, chunk, n, idx);
+    else
+        return ld<T>(base, chunk, n, idx);
+}
 template <int F>
 struct Clo;
 template <>
 struct Clo<CLO_F64> {
-    template <class R>
+    template <class R, bool NT = false>
     __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
-            const double2 t = ld<double2>(static_cast<const double2 *>(base) + (size_t)h * 18 * n, k, n, at);
+            const double2 t = ldc<double2, NT>(static_cast<const double2 *>(base) + (size_t)h * 18 * n, k, n, at);
             a[2 * k] = R(t.x);
             a[2 * k + 1] = R(t.y);
         }
@@ -268,11 +286,11 @@ struct Clo<CLO_F64> {
 };
 template <>
 struct Clo<CLO_F32> {
-    template <class R>
+    template <class R, bool NT = false>
     __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const float4 t = ld<float4>(static_cast<const float4 *>(base) + (size_t)h * 9 * n, k, n, at);
+            const float4 t = ldc<float4, NT>(static_cast<const float4 *>(base) + (size_t)h * 9 * n, k, n, at);
             a[4 * k] = R(t.x);
             a[4 * k + 1] = R(t.y);
             a[4 * k + 2] = R(t.z);
@@ -282,11 +300,11 @@ struct Clo<CLO_F32> {
 };
 template <>
 struct Clo<CLO_F16> {
-    template <class R>
+    template <class R, bool NT = false>
     __device__ static inline void load_half(const void *base, long n, unsigned at, int h, R a[36]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const h4 t = ld<h4>(static_cast<const h4 *>(base) + (size_t)h * 9 * n, k, n, at);
+            const h4 t = ldc<h4, NT>(static_cast<const h4 *>(base) + (size_t)h * 9 * n, k, n, at);
 #pragma unroll
             for (int e = 0; e < 4; ++e) a[4 * k + e] = R(__half2float(t.v[e]));
         }
@@ -312,12 +330,12 @@ __device__ inline void herm6_apply(const R *h, const cx<R> v[6], cx<R> out[6]) {
 
 // out = A v for the clover of site `at` of a table with n entries, read and
 // applied one chirality half at a time.
-template <int CF, class R>
+template <int CF, class R, bool NT = false>
 __device__ inline void clover_apply(const void *clo, long n, unsigned at, const cx<R> v[12], cx<R> out[12]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         R a[36];
-        Clo<CF>::load_half(clo, n, at, h, a);
+        Clo<CF>::template load_half<R, NT>(clo, n, at, h, a);
         herm6_apply(a, v + 6 * h, out + 6 * h);
     }
 }
@@ -393,6 +411,24 @@ __device__ inline void hop(const cx<R> w[9], const cx<R> psi[12], R sign, cx<R> 
     project<R, MU, S>(psi, h);
     su3_mul2<R, !FWD>(w, h, g);
     reconstruct_add<R, MU, S>(g, sign, acc);
+}
+
+// XCD-aware order of a 2D grid.  Workgroups are dispatched round-robin over
+// the 8 XCDs (each with its own L2) by linear id; this maps them so that XCD k
+// gets the k-th contiguous eighth of the logical grid, with all y (right-hand
+// side groups) of one x (site tile or Schwarz block) adjacent, so that link,
+// clover and neighbour data are reused inside one L2.
+__device__ inline void xcd_order(unsigned &x, unsigned &y) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, tot = gx * gy;
+    if (tot % 8u) {
+        x = blockIdx.x;
+        y = blockIdx.y;
+        return;
+    }
+    const unsigned w = blockIdx.x + blockIdx.y * gx;
+    const unsigned L = (w & 7u) * (tot >> 3) + (w >> 3);
+    x = L / gy;
+    y = L - x * gy;
 }
 
 // neighbour table: entry of site x in direction d = 2 mu + (0 fwd | 1 bwd);

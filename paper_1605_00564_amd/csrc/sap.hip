@@ -99,17 +99,18 @@ __global__ void __launch_bounds__(MAXT)
     __shared__ R red[16][3];
     const int NT = blockDim.x;
     const int tid = threadIdx.x;
-    const int rhs = blockIdx.y;
+    unsigned bx, rhs;
+    xcd_order(bx, rhs);
     const size_t fs = (size_t)Spin<S>::NCH * V * 16;
     const void *eta = static_cast<const char *>(eta_all) + rhs * fs;
     void *psi = static_cast<char *>(psi_all) + rhs * fs;
-    const long B = (long)colour * nbc + blockIdx.x;
+    const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
     cx<R> *Rb, *Tb;
     if (LDS) {
         Rb = reinterpret_cast<cx<R> *>(dsm);
     } else {
-        Rb = gbuf + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (size_t)24 * Vbh;
+        Rb = gbuf + ((size_t)rhs * gridDim.x + bx) * (size_t)24 * Vbh;
     }
     Tb = Rb + 12 * Vbh;
 
