@@ -145,14 +145,20 @@ __global__ void __launch_bounds__(BLAS_BS) k_resid(const double2 *__restrict__ b
     block_partials<1>(acc, part, gridDim.x);
 }
 
-// out[rhs][v] = sum over blocks of part[rhs][v][blk], fixed order
-__global__ void k_reduce(const double *__restrict__ part, int nv, int nblk, int n, double *__restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// out[rhs][v] = sum over blocks of part[rhs][v][blk]: one wave per value,
+// lane j sums partials j, j+64, ... and a fixed butterfly combines the
+// lanes, so the order of additions (and the result) never changes
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part, int nv, int nblk, int n,
+                                                double *__restrict__ out) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= n * nv) return;
     const double *p = part + (size_t)t * nblk;
     double s = 0;
-    for (int b = 0; b < nblk; ++b) s += p[b];
-    out[t] = s;
+    for (int b = lane; b < nblk; b += 64) s += p[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[t] = s;
 }
 
 // FP64 internal spinor (12 chunks of one complex) <-> FP32 internal spinor
@@ -287,7 +293,7 @@ static int grid_blocks(long ne) {
 
 int blas_reduce(const double *part, int nv, int nblk, int n, double *out, hipStream_t s) {
     const int tot = n * nv;
-    k_reduce<<<(tot + 127) / 128, 128, 0, s>>>(part, nv, nblk, n, out);
+    k_reduce<<<(tot + 3) / 4, 256, 0, s>>>(part, nv, nblk, n, out);
     DFL_HIP(hipGetLastError());
     return 0;
 }

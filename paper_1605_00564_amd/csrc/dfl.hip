@@ -203,67 +203,6 @@ __global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ 
     Spin<double>::store(out, V, x, h);
 }
 
-// u[r][B][l] = (phi_{B,l}, v_r) over the block's sites.  One workgroup per
-// (block, rhs); E = float4 (FP32 vector) or double2 (FP64 vector).
-template <class E>
-__device__ inline void rdot(const float4 &f, const E *v, long i0, long i1, double &re, double &im);
-template <>
-__device__ inline void rdot<float4>(const float4 &f, const float4 *v, long i0, long, double &re, double &im) {
-    const float4 b = v[i0];
-    re += (double)f.x * b.x + (double)f.y * b.y + (double)f.z * b.z + (double)f.w * b.w;
-    im += (double)f.x * b.y - (double)f.y * b.x + (double)f.z * b.w - (double)f.w * b.z;
-}
-template <>
-__device__ inline void rdot<double2>(const float4 &f, const double2 *v, long i0, long i1, double &re, double &im) {
-    const double2 a = v[i0], b = v[i1];
-    re += (double)f.x * a.x + (double)f.y * a.y + (double)f.z * b.x + (double)f.w * b.y;
-    im += (double)f.x * a.y - (double)f.y * a.x + (double)f.z * b.y - (double)f.w * b.x;
-}
-
-// FP64-accumulated restriction, tiles of RL fields x RR right-hand sides per
-// pass over the block (used for FP64 vectors: little-operator assembly and
-// the low-mode corrections of the outer loop).
-constexpr int RL = 4, RR = 4;
-template <class E>
-__global__ void __launch_bounds__(256) k_restrict(const E *__restrict__ v, const float4 *__restrict__ phi,
-                                                  const int *__restrict__ boff, double2 *__restrict__ u, long V,
-                                                  long Vh, int Vbh, int Ns, int Nb, int n) {
-    const int B = blockIdx.x, r0 = blockIdx.y * RR;
-    const long per = 12L * Vbh;
-    constexpr int NCH = sizeof(E) == 16 && sizeof(((E *)0)->x) == 4 ? 6 : 12;
-    const long bo = boff[B];
-    for (int l0 = 0; l0 < Ns; l0 += RL) {
-        double d[2 * RL * RR], od[2 * RL * RR];
-#pragma unroll
-        for (int q = 0; q < 2 * RL * RR; ++q) d[q] = 0;
-        for (long q = threadIdx.x; q < per; q += blockDim.x) {
-            const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-            const long site = p * Vh + bo + j;
-#pragma unroll
-            for (int a = 0; a < RL; ++a) {
-                if (l0 + a >= Ns) break;
-                const float4 f = phi[((size_t)B * Ns + l0 + a) * per + q];
-#pragma unroll
-                for (int b = 0; b < RR; ++b) {
-                    if (r0 + b >= n) break;
-                    const E *vr = v + (size_t)(r0 + b) * NCH * V;
-                    double &re = d[2 * (a * RR + b)], &im = d[2 * (a * RR + b) + 1];
-                    if (NCH == 6)
-                        rdot<E>(f, vr, (long)c * V + site, 0, re, im);
-                    else
-                        rdot<E>(f, vr, (long)(2 * c) * V + site, (long)(2 * c + 1) * V + site, re, im);
-                }
-            }
-        }
-        wg_sum<2 * RL * RR>(d, od);
-        if (threadIdx.x < RL * RR) {
-            const int a = threadIdx.x / RR, b = threadIdx.x % RR;
-            if (l0 + a < Ns && r0 + b < n)
-                u[((size_t)(r0 + b) * Nb + B) * Ns + l0 + a] = make_double2(od[2 * threadIdx.x], od[2 * threadIdx.x + 1]);
-        }
-    }
-}
-
 // FP32 restriction u = Phi^+ v as a real GEMM on the matrix cores
 // (v_mfma_f32_16x16x4f32, FP32 accumulation).  Rows: 16 deflation fields;
 // columns: 8 right-hand sides x (re, im); K: the real components of the
@@ -274,6 +213,7 @@ __global__ void __launch_bounds__(256) k_restrict(const E *__restrict__ v, const
 // float4 (two complex) of phi and of v per four MFMAs; the K order is
 // (element q + L / 16, component i), identical for both operands.
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict__ v, const float4 *__restrict__ phi,
                                                        const int *__restrict__ boff, double2 *__restrict__ u, long V,
                                                        long Vh, int Vbh, int Ns, int Nb, int n) {
@@ -326,22 +266,90 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict_
     }
 }
 
+// FP64 restriction u = Phi^+ v for FP64 vectors on the FP64 matrix cores
+// (little-operator assembly and the outer loop's low-mode corrections).
+// Per block a complex GEMM (Ns x 24 Vb) (24 Vb x n): with phi = a + ib and
+// v = c + id, conj(phi) v = (ac + bd) + i(ad - bc), accumulated as four real
+// 16x16x4 products.  Rows: 16 fields; columns: 16 right-hand sides; lane L
+// supplies phi[row L % 16][k L / 16] and v[k L / 16][rhs L % 16] (k: one
+// float4 element = two complex, one MFMA quadruple each) and receives
+// u[field L / 16 + 4 i][rhs L % 16], i = 0..3.  The four waves
+// take every fourth group of four elements; their partial sums are added in
+// a fixed order.
+__global__ void __launch_bounds__(256) k_restrict_mfma64(const double2 *__restrict__ v, const float4 *__restrict__ phi,
+                                                         const int *__restrict__ boff, double2 *__restrict__ u, long V,
+                                                         long Vh, int Vbh, int Ns, int Nb, int n) {
+    __shared__ double red[4][2][16][17];
+    const int B = blockIdx.x, r0 = blockIdx.y * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kk = lane >> 4;
+    const long per = 12L * Vbh;
+    const long bo = boff[B];
+    const bool rv = r0 + row < n;
+    const double2 *vr = v + (size_t)(rv ? r0 + row : 0) * 12 * V;
+    for (int l0 = 0; l0 < Ns; l0 += 16) {
+        const bool lv = l0 + row < Ns;
+        const float4 *pl = phi + ((size_t)B * Ns + (lv ? l0 + row : 0)) * per;
+        d4v ac = {0, 0, 0, 0}, bd = {0, 0, 0, 0}, ad = {0, 0, 0, 0}, bc = {0, 0, 0, 0};
+        for (long q0 = (long)wave * 4; q0 < per; q0 += 16) {
+            const long q = q0 + kk;
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+            double2 b0 = make_double2(0.0, 0.0), b1 = make_double2(0.0, 0.0);
+            if (q < per) {
+                if (lv) a = pl[q];
+                if (rv) {
+                    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
+                    const long site = p * Vh + bo + j;
+                    b0 = vr[(long)(2 * c) * V + site];
+                    b1 = vr[(long)(2 * c + 1) * V + site];
+                }
+            }
+            ac = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.x, b0.x, ac, 0, 0, 0);
+            bd = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.y, b0.y, bd, 0, 0, 0);
+            ad = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.x, b0.y, ad, 0, 0, 0);
+            bc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.y, b0.x, bc, 0, 0, 0);
+            ac = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.z, b1.x, ac, 0, 0, 0);
+            bd = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.w, b1.y, bd, 0, 0, 0);
+            ad = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.z, b1.y, ad, 0, 0, 0);
+            bc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a.w, b1.x, bc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            red[wave][0][kk + 4 * i][row] = ac[i] + bd[i];
+            red[wave][1][kk + 4 * i][row] = ad[i] - bc[i];
+        }
+        __syncthreads();
+        {
+            const int orow = threadIdx.x >> 4, orr = threadIdx.x & 15;
+            if (l0 + orow < Ns && r0 + orr < n) {
+                double re = 0, im = 0;
+                for (int w = 0; w < 4; ++w) {
+                    re += red[w][0][orow][orr];
+                    im += red[w][1][orow][orr];
+                }
+                u[((size_t)(r0 + orr) * Nb + B) * Ns + l0 + orow] = make_double2(re, im);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // v_r (op)= sum_l phi_{B,l} c[r][B][l]; MODE 0: v = .., 1: v -= .., 2: v += ..
 // Each thread owns one float4 element (two complex) of a block and PR
-// right-hand sides, so phi is read once per PR vectors; the coefficients of
-// a block are uniform across the workgroup.
-constexpr int PR = 8;
+// right-hand sides, so phi is read once per PR vectors.  A workgroup covers
+// one chunk of 256 elements of one block (grid.x = blocks x chunks), so the
+// block's coefficients are uniform and held in scalar registers.
+constexpr int PR = 12;
 template <class E, int MODE>
 __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4 *__restrict__ phi,
                                                  const int *__restrict__ boff, const double2 *__restrict__ cf,
-                                                 long V, long Vh, int Vbh, int Ns, int Nb, int n) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                 long V, long Vh, int Vbh, int Ns, int Nb, int n, int nchunk) {
+    const int B = blockIdx.x / nchunk;
     const long per = 12L * Vbh;
-    if (t >= (long)Nb * per) return;
+    const long q = (long)(blockIdx.x - B * nchunk) * 256 + threadIdx.x;
+    if (q >= per) return;
     const int r0 = blockIdx.y * PR;
     const int nr = min(PR, n - r0);
-    const int B = (int)(t / per);
-    const long q = t % per;
     const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
     const long site = p * Vh + boff[B] + j;
     double ar[PR], ai[PR], br[PR], bi[PR];
@@ -381,68 +389,55 @@ __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4
     }
 }
 
-// w[r][B][k] = sum_d sum_l A[B][d][k][l] v[r][nbr(B,d)][l].  One thread per
-// (B, k) row and up to LR right-hand sides (grid.y covers the rest), so each
-// row of A is read once per LR vectors.
-constexpr int LR = 8;
-__global__ void __launch_bounds__(128) k_little_apply(const double2 *__restrict__ A, const int *__restrict__ bnbr,
-                                                      const double2 *__restrict__ v, double2 *__restrict__ w,
-                                                      int Nb, int Ns, int n) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)Nb * Ns) return;
-    const int r0 = blockIdx.y * LR;
-    const int nr = min(LR, n - r0);
-    const int B = (int)(t / Ns), k = (int)(t % Ns);
+// w[r][B] = sum_{d < ND} M[B][d] v[r][nb(B, d)] with Ns x Ns complex blocks
+// M[B][d] (ND = 9: the little operator, neighbour d of block B from the
+// table; ND = 1: the block-Jacobi inverse acting on block B itself).  Per
+// block this is a complex GEMM (Ns x ND Ns) (ND Ns x n) on the FP64 matrix
+// cores: a wave owns one block, 16 rows and 16 right-hand sides, and with
+// M = a + ib, v = c + id accumulates Re w = a c - b d and Im w = a d + b c
+// as real 16x16x4 products over four complex elements of K at a time.  Lane
+// L supplies M[row L % 16][k L / 16] and v[k L / 16][rhs L % 16] and
+// receives w[row L / 16 + 4 i][rhs L % 16], i = 0..3 (the FP64 product's
+// result layout; the FP32 16x16x4 product returns row 4 (L / 16) + i).
+template <int ND>
+__global__ void __launch_bounds__(256) k_little_mfma(const double2 *__restrict__ M, const int *__restrict__ bnbr,
+                                                     const double2 *__restrict__ v, double2 *__restrict__ w,
+                                                     int Nb, int Ns, int n, int nmt, int nrt) {
+    const int lane = threadIdx.x & 63;
+    const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long per_block = (long)nmt * nrt;
+    if (wid >= (long)Nb * per_block) return;
+    const int B = (int)(wid / per_block);
+    const int rem = (int)(wid - (long)B * per_block);
+    const int m0 = (rem / nrt) * 16, r0 = (rem % nrt) * 16;
+    const int row = lane & 15, kk = lane >> 4;
+    const int m = m0 + row, r = r0 + row;
+    const bool mv = m < Ns, rv = r < n;
     const size_t N = (size_t)Nb * Ns;
-    double sr[LR], si[LR];
-#pragma unroll
-    for (int q = 0; q < LR; ++q) sr[q] = si[q] = 0;
-    for (int d = 0; d < 9; ++d) {
-        const double2 *a = A + (((size_t)B * 9 + d) * Ns + k) * Ns;
-        const double2 *x = v + (size_t)r0 * N + (size_t)bnbr[B * 9 + d] * Ns;
-        for (int l = 0; l < Ns; ++l) {
-            const double2 aa = a[l];
-#pragma unroll
-            for (int q = 0; q < LR; ++q)
-                if (q < nr) {
-                    const double2 xx = x[q * N + l];
-                    sr[q] += aa.x * xx.x - aa.y * xx.y;
-                    si[q] += aa.x * xx.y + aa.y * xx.x;
-                }
+    d4v ac = {0, 0, 0, 0}, bd = {0, 0, 0, 0}, ad = {0, 0, 0, 0}, bc = {0, 0, 0, 0};
+    for (int d = 0; d < ND; ++d) {
+        const double2 *Md = M + ((size_t)B * ND + d) * Ns * Ns + (size_t)(mv ? m : 0) * Ns;
+        const int nb = ND == 1 ? B : bnbr[B * 9 + d];
+        const double2 *vd = v + (size_t)(rv ? r : 0) * N + (size_t)nb * Ns;
+        for (int l0 = 0; l0 < Ns; l0 += 4) {
+            const int l = l0 + kk;
+            double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+            if (l < Ns) {
+                if (mv) a = Md[l];
+                if (rv) b = vd[l];
+            }
+            ac = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, ac, 0, 0, 0);
+            bd = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, bd, 0, 0, 0);
+            ad = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ad, 0, 0, 0);
+            bc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, bc, 0, 0, 0);
         }
     }
+    if (!rv) return;
 #pragma unroll
-    for (int q = 0; q < LR; ++q)
-        if (q < nr) w[(size_t)(r0 + q) * N + t] = make_double2(sr[q], si[q]);
-}
-
-// z[r][B] = Dinv[B] v[r][B]
-__global__ void __launch_bounds__(128) k_little_jacobi(const double2 *__restrict__ Dinv, const double2 *__restrict__ v,
-                                                       double2 *__restrict__ z, int Nb, int Ns, int n) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)Nb * Ns) return;
-    const int r0 = blockIdx.y * LR;
-    const int nr = min(LR, n - r0);
-    const int B = (int)(t / Ns), k = (int)(t % Ns);
-    const size_t N = (size_t)Nb * Ns;
-    const double2 *a = Dinv + ((size_t)B * Ns + k) * Ns;
-    const double2 *x = v + (size_t)r0 * N + (size_t)B * Ns;
-    double sr[LR], si[LR];
-#pragma unroll
-    for (int q = 0; q < LR; ++q) sr[q] = si[q] = 0;
-    for (int l = 0; l < Ns; ++l) {
-        const double2 aa = a[l];
-#pragma unroll
-        for (int q = 0; q < LR; ++q)
-            if (q < nr) {
-                const double2 xx = x[q * N + l];
-                sr[q] += aa.x * xx.x - aa.y * xx.y;
-                si[q] += aa.x * xx.y + aa.y * xx.x;
-            }
+    for (int i = 0; i < 4; ++i) {
+        const int mo = m0 + kk + 4 * i;
+        if (mo < Ns) w[(size_t)r * N + (size_t)B * Ns + mo] = make_double2(ac[i] - bd[i], ad[i] + bc[i]);
     }
-#pragma unroll
-    for (int q = 0; q < LR; ++q)
-        if (q < nr) z[(size_t)(r0 + q) * N + t] = make_double2(sr[q], si[q]);
 }
 
 // Dinv[B] = A[B][0]^{-1}: Gauss-Jordan with partial pivoting, one thread per
@@ -607,8 +602,8 @@ int restrict_v(qcd_dfl d, const E *v, double2 *u, int n, hipStream_t s) {
         k_restrict_mfma<<<dim3(d->Nb, (n + 7) / 8), 256, 0, s>>>(reinterpret_cast<const float4 *>(v), d->phi, d->boff,
                                                                   u, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n);
     else
-        k_restrict<E><<<dim3(d->Nb, (n + RR - 1) / RR), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns,
-                                                                      d->Nb, n);
+        k_restrict_mfma64<<<dim3(d->Nb, (n + 15) / 16), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns,
+                                                                    d->Nb, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -620,29 +615,36 @@ int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
     double fl, by;
     dfl_work_counts(d, n, (F32V ? 96 : 192) * (MODE == 0 ? 1 : 2), fl, by);
     ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
-    const long tot = (long)d->Nb * 12 * g.Vbh;
-    k_prolong<E, MODE><<<dim3(nblocks(tot, 256), (n + PR - 1) / PR), 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh,
-                                                                                   g.Vbh, d->Ns, d->Nb, n);
+    const int nchunk = (int)nblocks(12L * g.Vbh, 256);
+    k_prolong<E, MODE><<<dim3((unsigned)(d->Nb * nchunk), (n + PR - 1) / PR), 256, 0, s>>>(
+        v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n, nchunk);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+template <int ND>
+static int launch_little(qcd_dfl d, const double2 *M, const double2 *v, double2 *w, int n, hipStream_t s) {
+    const int nmt = (d->Ns + 15) / 16, nrt = (n + 15) / 16;
+    const long waves = (long)d->Nb * nmt * nrt;
+    k_little_mfma<ND><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(M, d->bnbr, v, w, d->Nb, d->Ns, n, nmt, nrt);
     DFL_HIP(hipGetLastError());
     return 0;
 }
 
 int little_apply_dev(qcd_dfl d, const double2 *v, double2 *w, int n, hipStream_t s) {
     const long N = (long)d->Nb * d->Ns;
-    // 9 Ns^2 complex multiply-adds per block row and rhs; A read once per LR rhs
+    // 9 Ns^2 complex multiply-adds per block row and rhs; A read once per 16
+    // right-hand sides, v and w once per rhs
     ProfScope ps(PROF_LITTLE, s, 8.0 * 9 * d->Ns * N * n,
-                 16.0 * (9.0 * d->Ns * N * ((n + LR - 1) / LR) + 2.0 * N * n), (double)N * n);
-    k_little_apply<<<dim3(nblocks(N, 128), (n + LR - 1) / LR), 128, 0, s>>>(d->A, d->bnbr, v, w, d->Nb, d->Ns, n);
-    DFL_HIP(hipGetLastError());
-    return 0;
+                 16.0 * (9.0 * d->Ns * N * ((n + 15) / 16) + 2.0 * N * n), (double)N * n);
+    return launch_little<9>(d, d->A, v, w, n, s);
 }
 
 int little_jacobi_dev(qcd_dfl d, const double2 *v, double2 *z, int n, hipStream_t s) {
     const long N = (long)d->Nb * d->Ns;
-    ProfScope ps(PROF_LITTLE, s, 8.0 * d->Ns * N * n, 16.0 * ((double)d->Ns * N + 2.0 * N * n), (double)N * n);
-    k_little_jacobi<<<dim3(nblocks(N, 128), (n + LR - 1) / LR), 128, 0, s>>>(d->Dinv, v, z, d->Nb, d->Ns, n);
-    DFL_HIP(hipGetLastError());
-    return 0;
+    ProfScope ps(PROF_LITTLE, s, 8.0 * d->Ns * N * n, 16.0 * ((double)d->Ns * N * ((n + 15) / 16) + 2.0 * N * n),
+                 (double)N * n);
+    return launch_little<1>(d, d->Dinv, v, z, n, s);
 }
 
 // x = A^{-1} u by block-Jacobi preconditioned GCR (FP64).  poll: check the

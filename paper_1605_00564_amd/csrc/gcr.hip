@@ -113,7 +113,12 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         return true;
     };
     const int limit = p->fixed_iters > 0 ? p->fixed_iters : p->nmx;
-    const double inner_rel = vin == QCD_F64 ? 0.0 : 1e-6;
+    // A cycle ends once its residual has dropped by inner_rel: with FP32
+    // Krylov vectors that is their precision limit; with deflation (in
+    // either precision) the next cycle's low-mode correction removes what
+    // the inexact little solves leave outside range(P_L), which the
+    // search directions cannot reach.
+    const double inner_rel = (vin == QCD_F64 && !p->dfl) ? 0.0 : 1e-6;
     int iters = 0;
     bool done = p->fixed_iters <= 0 && converged(rn);
     while (!done && iters < limit) {
