@@ -148,6 +148,35 @@ def fp64_single_rhs(fld, d, pos, npos, setup_s, little_maxit, log):
             "sample": "12 sloppy and 12 exact single-rhs FP64 solves at one position, scaled to all positions"}
 
 
+KERNEL_SOURCES = {
+    "k_sap_sweep": ["paper_1605_00564_amd/csrc/sap.hip", "paper_1605_00564_amd/csrc/internal.h"],
+    "k_dirac_rg": ["paper_1605_00564_amd/csrc/dirac.hip", "paper_1605_00564_amd/csrc/internal.h"],
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
+    counter reads for an elementwise kernel of known size), or None when there
+    is no summary or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.txt")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if not line.startswith((" ", "#")) and ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.split()[0] if v.split() else ""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def stencil_sweep(lattices, storages, nrhs_list, reps, log):
     """Dirac-operator GB/s and Gflop/s per storage mode and right-hand-side
     count (kernel time from HIP events; pack/unpack kernels excluded)."""
@@ -226,10 +255,16 @@ def main():
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             torch.mul(a, 1.0, out=b)    # one elementwise kernel: reads a, writes b
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "copies": 5}), flush=True)
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "copies": 5, "ms_per_copy": ms,
+                          "GB/s": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
         return
     if args.stencil_sweep:
         lats = [tuple(int(v) for v in s.split("x")) for s in args.sweep_lattices.split(",")]
@@ -330,7 +365,9 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = {"sap": "k_sap_sweep", "dirac": "k_dirac", "blas": "vector algebra"}.get(dom, dom)
+    roof["kernel"] = {"sap": "k_sap_sweep", "dirac": "k_dirac_rg", "blas": "vector algebra"}.get(dom, dom)
+    roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
+    roof["traffic_unit"] = "bytes per launch"
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = P["launches"]
     # stencil figures (the Dirac-operator half of the metric)
@@ -342,6 +379,8 @@ def main():
                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "gflops": Pd["flops"] / (Pd["ms"] * 1e-3) / 1e9,
                    "avg_launch_ms": dms, "launches": Pd["launches"]}
         stencil["frac"] = stencil["achieved"] / PEAK_HBM_GBS
+        stencil["traffic"] = measured_traffic("k_dirac_rg", args.workload)
+        stencil["traffic_unit"] = "bytes per launch"
 
     infs, infe = state["infs"], state["infe"]
     result = {

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ 
     Spin<float>::load(in, V, x, p);
     clover_apply<CLO_F64>(clo, V, x, p, h);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[k] = h[k] - kappa * acc[k];
+    for (int k = 0; k < 12; ++k) h[k] = rmac(h[k], -kappa, acc[k]);
     Spin<double>::store(out, V, x, h);
 }
 

@@ -194,9 +194,45 @@ __global__ void k_nbr_table(Geom g, int bc_t, const int *__restrict__ int_of, in
 // ---------------------------------------------------------------------------
 // link packing: canonical complex128 [V][4][3][3] -> storage copies
 // ---------------------------------------------------------------------------
+__device__ inline __half to_h(double x) { return __float2half((float)x); }
+__device__ inline __hip_bfloat16 to_b(double x) { return __float2bfloat16((float)x); }
+
+// F16R / BF16R link: rows 0 and 1 rounded to the half type, row 2 =
+// conj(row0 x row1) of the rounded rows in FP64, stored in FP32
+template <class H, class H8, class H4>
+__device__ inline void pack_link_r(const double2 w[9], H (*rnd)(double), float4 *dst, long V, long idx) {
+    H8 c0;
+    H4 c1h;
+    double2 a[6];
+    for (int k = 0; k < 6; ++k) {
+        const H re = rnd(w[k].x), im = rnd(w[k].y);
+        a[k] = make_double2(to_f(re), to_f(im));
+        if (k < 4) {
+            c0.v[2 * k] = re;
+            c0.v[2 * k + 1] = im;
+        } else {
+            c1h.v[2 * (k - 4)] = re;
+            c1h.v[2 * (k - 4) + 1] = im;
+        }
+    }
+    auto mul = [](double2 x, double2 y) { return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x); };
+    auto sub_conj = [](double2 x, double2 y) { return make_double2(x.x - y.x, -(x.y - y.y)); };
+    const double2 w6 = sub_conj(mul(a[1], a[5]), mul(a[2], a[4]));
+    const double2 w7 = sub_conj(mul(a[2], a[3]), mul(a[0], a[5]));
+    const double2 w8 = sub_conj(mul(a[0], a[4]), mul(a[1], a[3]));
+    float4 f0, f1;
+    __builtin_memcpy(&f0, &c0, sizeof(float4));
+    __builtin_memcpy(&f1, &c1h, sizeof(H4));
+    f1.z = (float)w6.x;
+    f1.w = (float)w6.y;
+    dst[0 * V + idx] = f0;
+    dst[1 * V + idx] = f1;
+    dst[2 * V + idx] = make_float4((float)w7.x, (float)w7.y, (float)w8.x, (float)w8.y);
+}
+
 __global__ void k_pack_links(const double2 *__restrict__ canon, const int *__restrict__ lex_of, long V,
                              double2 *__restrict__ u64, float4 *__restrict__ u32, h4 *__restrict__ u16,
-                             b4 *__restrict__ ubf) {
+                             b4 *__restrict__ ubf, float4 *__restrict__ u16r, float4 *__restrict__ ubfr) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= V) return;
     long i = lex_of[idx];
@@ -205,6 +241,8 @@ __global__ void k_pack_links(const double2 *__restrict__ canon, const int *__res
         double2 w[9];
         for (int k = 0; k < 9; ++k) w[k] = src[k];
         for (int k = 0; k < 9; ++k) u64[((long)mu * 9 + k) * V + idx] = w[k];
+        pack_link_r<__half, h8, h4>(w, to_h, u16r + (long)mu * 3 * V, V, idx);
+        pack_link_r<__hip_bfloat16, b8, b4>(w, to_b, ubfr + (long)mu * 3 * V, V, idx);
         for (int c = 0; c < 3; ++c) {
             double2 a = w[2 * c], b = w[2 * c + 1];
             u32[((long)mu * 3 + c) * V + idx] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
@@ -465,11 +503,14 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     ALLOC(f->lnbr, sizeof(short) * 16 * g.Vbh);
     ALLOC(f->int_of, sizeof(int) * V);
     ALLOC(f->lex_of, sizeof(int) * V);
+    ALLOC(f->border, sizeof(int) * g.Nb);
     ALLOC(f->flag, sizeof(int));
     ALLOC(f->U[LNK_F64], sizeof(double2) * 36 * V);
     ALLOC(f->U[LNK_F32], sizeof(float4) * 12 * V);
     ALLOC(f->U[LNK_F16], sizeof(h4) * 12 * V);
     ALLOC(f->U[LNK_BF16], sizeof(b4) * 12 * V);
+    ALLOC(f->U[LNK_F16R], sizeof(float4) * 12 * V);
+    ALLOC(f->U[LNK_BF16R], sizeof(float4) * 12 * V);
     ALLOC(f->clo[CLO_F64], sizeof(double2) * 36 * V);
     ALLOC(f->clo[CLO_F32], sizeof(float4) * 18 * V);
     ALLOC(f->clo[CLO_F16], sizeof(h4) * 18 * V);
@@ -502,7 +543,18 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
             }
     }
     if (g.Vbh > 32767) return fail(set_error(QCD_EINVAL, "Schwarz block too large"));
+    // blocks in lexicographic order -> their place in the colour-major layout
+    std::vector<int> bord(g.Nb);
+    for (int Bl = 0; Bl < g.Nb; ++Bl) {
+        int r = Bl, bsum = 0;
+        for (int m = 3; m >= 0; --m) {
+            bsum += r % g.nb[m];
+            r /= g.nb[m];
+        }
+        bord[Bl] = (bsum & 1) * (g.Nb / 2) + Bl / 2;
+    }
     hipError_t e = hipMemcpyAsync(f->lnbr, lnb.data(), sizeof(short) * lnb.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->border, bord.data(), sizeof(int) * bord.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
     {
@@ -511,7 +563,8 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         k_nbr_table<<<nblocks(V, 256), 256, 0, s>>>(g, lat->bc_t, f->int_of, f->nbr);
         k_pack_links<<<nblocks(V, 256), 256, 0, s>>>(canon, f->lex_of, V, (double2 *)f->U[LNK_F64],
                                                     (float4 *)f->U[LNK_F32], (h4 *)f->U[LNK_F16],
-                                                    (b4 *)f->U[LNK_BF16]);
+                                                    (b4 *)f->U[LNK_BF16], (float4 *)f->U[LNK_F16R],
+                                                    (float4 *)f->U[LNK_BF16R]);
         k_clover<<<nblocks(V, 128), 128, 0, s>>>((const double2 *)f->U[LNK_F64], f->nbr, V, Vh, lat->kappa,
                                                  lat->csw, (double2 *)f->clo[CLO_F64], (float4 *)f->clo[CLO_F32],
                                                  (h4 *)f->clo[CLO_F16], (double2 *)f->cloinv[CLO_F64],
@@ -556,6 +609,7 @@ int qcd_field_destroy(qcd_field f) {
     if (!f) return 0;
     (void)hipFree(f->nbr);
     (void)hipFree(f->lnbr);
+    (void)hipFree(f->border);
     (void)hipFree(f->int_of);
     (void)hipFree(f->lex_of);
     (void)hipFree(f->flag);

@@ -91,14 +91,41 @@ __host__ __device__ inline cx<R> imul(cx<R> a) { return {-a.im, a.re}; }
 template <class R>
 __host__ __device__ inline R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 
+// Multiply-accumulate as explicit fused multiply-adds: written as
+// acc + (a b - c d) the compiler must keep a separate product and sum (it
+// may not reassociate), and 0 + x cannot be folded under signed zeros, so
+// sums start from their first product and continue with four FMAs per term.
+__host__ __device__ inline float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ inline double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a b
+template <class R>
+__host__ __device__ inline cx<R> cmac(cx<R> acc, cx<R> a, cx<R> b) {
+    return {ffma(-a.im, b.im, ffma(a.re, b.re, acc.re)), ffma(a.im, b.re, ffma(a.re, b.im, acc.im))};
+}
+// acc + conj(a) b
+template <class R>
+__host__ __device__ inline cx<R> cmacc(cx<R> acc, cx<R> a, cx<R> b) {
+    return {ffma(a.im, b.im, ffma(a.re, b.re, acc.re)), ffma(-a.im, b.re, ffma(a.re, b.im, acc.im))};
+}
+// acc + s a (s real)
+template <class R>
+__host__ __device__ inline cx<R> rmac(cx<R> acc, R s, cx<R> a) {
+    return {ffma(s, a.re, acc.re), ffma(s, a.im, acc.im)};
+}
+
 // ---------------------------------------------------------------------------
 // storage formats
 // ---------------------------------------------------------------------------
 struct alignas(8) h4 { __half v[4]; };        // 2 complex in FP16
 struct alignas(8) b4 { __hip_bfloat16 v[4]; }; // 2 complex in BF16
 struct alignas(16) h8 { __half v[8]; };       // 4 complex in FP16
+struct alignas(16) b8 { __hip_bfloat16 v[8]; }; // 4 complex in BF16
 
-enum LinkFmt { LNK_F64 = 0, LNK_F32 = 1, LNK_F16 = 2, LNK_BF16 = 3 };
+// F16R / BF16R: rows 0 and 1 in FP16 / BF16 and row 2 stored in FP32,
+// computed once as conj(row0 x row1) from the rounded rows: the same matrix
+// as the reconstruct-12 format, without the per-use reconstruction (for the
+// ALU-bound Schwarz kernel, which reads each link many times).
+enum LinkFmt { LNK_F64 = 0, LNK_F32 = 1, LNK_F16 = 2, LNK_BF16 = 3, LNK_F16R = 4, LNK_BF16R = 5 };
 enum CloFmt { CLO_F64 = 0, CLO_F32 = 1, CLO_F16 = 2 };
 
 // Device-memory tables are read and written through buffer instructions:
@@ -217,9 +244,9 @@ struct Link<LNK_F64> {
 template <class R>
 __device__ inline void rebuild_row2(cx<R> w[9]) {
     // row2 = conj(row0 x row1)
-    w[6] = conj(w[1] * w[5] - w[2] * w[4]);
-    w[7] = conj(w[2] * w[3] - w[0] * w[5]);
-    w[8] = conj(w[0] * w[4] - w[1] * w[3]);
+    w[6] = conj(cmac(w[1] * w[5], -w[2], w[4]));
+    w[7] = conj(cmac(w[2] * w[3], -w[0], w[5]));
+    w[8] = conj(cmac(w[0] * w[4], -w[1], w[3]));
 }
 template <>
 struct Link<LNK_F32> {
@@ -260,6 +287,34 @@ struct Link<LNK_BF16> {
         rebuild_row2(w);
     }
 };
+
+// [mu][3 chunks of 16 B][V]: chunk 0 = w0..w3 in the half type, chunk 1 =
+// w4, w5 (half type) and w6 (FP32), chunk 2 = w7, w8 (FP32)
+__device__ inline float to_f(__half x) { return __half2float(x); }
+__device__ inline float to_f(__hip_bfloat16 x) { return __bfloat162float(x); }
+template <class H4, class H8>
+struct LinkR {
+    template <class R>
+    __device__ static inline void load(const void *base, long V, int mu, unsigned idx, cx<R> w[9]) {
+        const float4 *b = static_cast<const float4 *>(base) + (size_t)mu * 3 * V;
+        const H8 t0 = ld<H8>(b, 0, V, idx);
+        const float4 t1 = ld<float4>(b, 1, V, idx);
+        const float4 t2 = ld<float4>(b, 2, V, idx);
+        H4 t1h;
+        __builtin_memcpy(&t1h, &t1, sizeof(H4));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = {R(to_f(t0.v[2 * k])), R(to_f(t0.v[2 * k + 1]))};
+        w[4] = {R(to_f(t1h.v[0])), R(to_f(t1h.v[1]))};
+        w[5] = {R(to_f(t1h.v[2])), R(to_f(t1h.v[3]))};
+        w[6] = {R(t1.z), R(t1.w)};
+        w[7] = {R(t2.x), R(t2.y)};
+        w[8] = {R(t2.z), R(t2.w)};
+    }
+};
+template <>
+struct Link<LNK_F16R> : LinkR<h4, h8> {};
+template <>
+struct Link<LNK_BF16R> : LinkR<b4, b8> {};
 
 // Clover access: one chirality half (36 reals) of a site's packed clover;
 // NT marks the loads non-temporal (clover read once per site by the stencil).
@@ -322,8 +377,8 @@ __device__ inline void herm6_apply(const R *h, const cx<R> v[6], cx<R> out[6]) {
 #pragma unroll
         for (int j = i + 1; j < 6; ++j) {
             cx<R> a = {h[6 + 2 * m], h[7 + 2 * m]};
-            out[i] = out[i] + a * v[j];
-            out[j] = out[j] + cmulc(a, v[i]);
+            out[i] = cmac(out[i], a, v[j]);
+            out[j] = cmacc(out[j], a, v[i]);
             ++m;
         }
 }
@@ -365,25 +420,33 @@ __device__ inline void project(const cx<R> p[12], cx<R> h[6]) {
     }
 }
 
+// acc + s i a (s real)
+template <class R>
+__device__ inline cx<R> imac(cx<R> acc, R s, cx<R> a) {
+    return {ffma(-s, a.im, acc.re), ffma(s, a.re, acc.im)};
+}
+
 template <class R, int MU, int S>
 __device__ inline void reconstruct_add(const cx<R> g[6], R sign, cx<R> acc[12]) {
+    // the hop's boundary sign enters through the FMAs (a constant 1 folds away)
+    const R sp = S > 0 ? sign : -sign, sm = -sp;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cx<R> g0 = sign * g[c], g1 = sign * g[3 + c];
-        acc[c] = acc[c] + g0;
-        acc[3 + c] = acc[3 + c] + g1;
+        const cx<R> g0 = g[c], g1 = g[3 + c];
+        acc[c] = rmac(acc[c], sign, g0);
+        acc[3 + c] = rmac(acc[3 + c], sign, g1);
         if (MU == 0) {  // (h0, h1, -s h0, -s h1)
-            acc[6 + c] = S > 0 ? acc[6 + c] - g0 : acc[6 + c] + g0;
-            acc[9 + c] = S > 0 ? acc[9 + c] - g1 : acc[9 + c] + g1;
+            acc[6 + c] = rmac(acc[6 + c], sm, g0);
+            acc[9 + c] = rmac(acc[9 + c], sm, g1);
         } else if (MU == 1) {  // (h0, h1, i s h1, i s h0)
-            acc[6 + c] = S > 0 ? acc[6 + c] + imul(g1) : acc[6 + c] - imul(g1);
-            acc[9 + c] = S > 0 ? acc[9 + c] + imul(g0) : acc[9 + c] - imul(g0);
+            acc[6 + c] = imac(acc[6 + c], sp, g1);
+            acc[9 + c] = imac(acc[9 + c], sp, g0);
         } else if (MU == 2) {  // (h0, h1, s h1, -s h0)
-            acc[6 + c] = S > 0 ? acc[6 + c] + g1 : acc[6 + c] - g1;
-            acc[9 + c] = S > 0 ? acc[9 + c] - g0 : acc[9 + c] + g0;
+            acc[6 + c] = rmac(acc[6 + c], sp, g1);
+            acc[9 + c] = rmac(acc[9 + c], sm, g0);
         } else {  // (h0, h1, i s h0, -i s h1)
-            acc[6 + c] = S > 0 ? acc[6 + c] + imul(g0) : acc[6 + c] - imul(g0);
-            acc[9 + c] = S > 0 ? acc[9 + c] - imul(g1) : acc[9 + c] + imul(g1);
+            acc[6 + c] = imac(acc[6 + c], sp, g0);
+            acc[9 + c] = imac(acc[9 + c], sm, g1);
         }
     }
 }
@@ -395,9 +458,10 @@ __device__ inline void su3_mul2(const cx<R> w[9], const cx<R> h[6], cx<R> g[6]) 
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            cx<R> acc = {R(0), R(0)};
+            cx<R> acc = DAG ? cmulc(w[a], h[3 * s]) : w[a * 3] * h[3 * s];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) acc = acc + (DAG ? cmulc(w[b * 3 + a], h[3 * s + b]) : w[a * 3 + b] * h[3 * s + b]);
+            for (int b = 1; b < 3; ++b)
+                acc = DAG ? cmacc(acc, w[b * 3 + a], h[3 * s + b]) : cmac(acc, w[a * 3 + b], h[3 * s + b]);
             g[3 * s + a] = acc;
         }
 }
@@ -411,6 +475,18 @@ __device__ inline void hop(const cx<R> w[9], const cx<R> psi[12], R sign, cx<R> 
     project<R, MU, S>(psi, h);
     su3_mul2<R, !FWD>(w, h, g);
     reconstruct_add<R, MU, S>(g, sign, acc);
+}
+
+// A pointer the caller knows to be the same in every lane, marked as such:
+// buffer loads need their descriptor in scalar registers, and where the
+// compiler cannot prove a base uniform it wraps each load in a loop over
+// the distinct values.
+template <class T>
+__device__ inline T *wave_uniform(T *p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
 }
 
 // XCD-aware order of a 2D grid.  Workgroups are dispatched round-robin over
@@ -457,7 +533,8 @@ struct qcd_field_s {
     short *lnbr = nullptr;   // [2 parity][Vbh][8]: in-block neighbour (local j) or -1; same for every block
     int *int_of = nullptr;   // [V] lexicographic -> internal
     int *lex_of = nullptr;   // [V] internal -> lexicographic
-    void *U[4] = {nullptr, nullptr, nullptr, nullptr};      // by LinkFmt
+    int *border = nullptr;   // [Nb] lexicographic block -> block index in memory (colour-major)
+    void *U[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // by LinkFmt
     void *clo[3] = {nullptr, nullptr, nullptr};             // by CloFmt, all sites
     void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
     // scratch buffers owned by the handle, one per purpose, grown on demand

@@ -86,7 +86,7 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
     Spin<S>::load(psi, V, x, p);
     clover_apply<CF>(clo, V, x, p, out);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) out[k] = out[k] - kappa * acc[k];
+    for (int k = 0; k < 12; ++k) out[k] = rmac(out[k], -kappa, acc[k]);
 }
 
 template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT>
@@ -102,8 +102,8 @@ __global__ void __launch_bounds__(MAXT)
     unsigned bx, rhs;
     xcd_order(bx, rhs);
     const size_t fs = (size_t)Spin<S>::NCH * V * 16;
-    const void *eta = static_cast<const char *>(eta_all) + rhs * fs;
-    void *psi = static_cast<char *>(psi_all) + rhs * fs;
+    const void *eta = wave_uniform(static_cast<const char *>(eta_all) + rhs * fs);
+    void *psi = wave_uniform(static_cast<char *>(psi_all) + rhs * fs);
     const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
     cx<R> *Rb, *Tb;
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(MAXT)
             block_hop<R, LF, false>(U, lnbr, V, Vh, boff, j, Vbh, Tb, acc);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                Rb[c * Vbh + j] = Rb[c * Vbh + j] + kappa * acc[c];
+                Rb[c * Vbh + j] = rmac(Rb[c * Vbh + j], kappa, acc[c]);
                 xe[k][c] = {R(0), R(0)};
             }
             const long xo_i = Vh + boff + j;
@@ -198,11 +198,12 @@ __global__ void __launch_bounds__(MAXT)
                 block_hop<R, LF, false>(U, lnbr, V, Vh, boff, j, Vbh, Tb, acc);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
-                    p[k][c] = p[k][c] - k2 * acc[c];
-                    const cx<R> q = cmulc(p[k][c], Rb[c * Vbh + j]);
-                    pr_re += q.re;
-                    pr_im += q.im;
-                    pp += norm2(p[k][c]);
+                    p[k][c] = rmac(p[k][c], -k2, acc[c]);
+                    const cx<R> rc = r[c];
+                    // (p, r) = sum conj(p) r and (p, p)
+                    pr_re = ffma(p[k][c].im, rc.im, ffma(p[k][c].re, rc.re, pr_re));
+                    pr_im = ffma(-p[k][c].im, rc.re, ffma(p[k][c].re, rc.im, pr_im));
+                    pp = ffma(p[k][c].im, p[k][c].im, ffma(p[k][c].re, p[k][c].re, pp));
                 }
             }
         }
@@ -230,8 +231,8 @@ __global__ void __launch_bounds__(MAXT)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const cx<R> rc = Rb[c * Vbh + j];
-                    xe[k][c] = xe[k][c] + alpha * rc;
-                    Rb[c * Vbh + j] = it + 1 < nmr ? rc - alpha * p[k][c] : xe[k][c];
+                    xe[k][c] = cmac(xe[k][c], alpha, rc);
+                    Rb[c * Vbh + j] = it + 1 < nmr ? cmac(rc, -alpha, p[k][c]) : xe[k][c];
                 }
             }
         }
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(MAXT)
             clover_apply<CF>(cinv, Vh, boff + j, acc, t);
             Spin<S>::load(psi, V, xo_i, q);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) q[c] = q[c] + kappa * t[c];
+            for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);
             Spin<S>::store(psi, V, xo_i, q);
             if (first) {
                 Spin<S>::store(psi, V, xe_i, xe[k]);
@@ -317,7 +318,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     double hops = 0;
     for (int m = 0; m < 4; ++m) hops += 2.0 * (g.b[m] - 1) / g.b[m];
     const double h = 165.0 * hops;
-    const double lbytes = LF == LNK_F64 ? 144 : LF == LNK_F32 ? 48 : 24;
+    const double lbytes = LF == LNK_F64 ? 144 : (LF == LNK_F16 || LF == LNK_BF16) ? 24 : 48;
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
     const double pairs = (double)nbc * Vbh * nrhs;
     {
@@ -360,8 +361,10 @@ int sap_internal(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, in
     switch (sap->storage) {
         case QCD_F64: return run_sap<double, double, LNK_F64, CLO_F64>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
         case QCD_F32: return run_sap<float, float, LNK_F32, CLO_F32>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
-        case QCD_F16: return run_sap<float, float, LNK_F16, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
-        case QCD_BF16: return run_sap<float, float, LNK_BF16, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        // FP16 / BF16 link storage enters the Schwarz kernel with row 2
+        // precomputed (the same matrices as the reconstruct-12 copies)
+        case QCD_F16: return run_sap<float, float, LNK_F16R, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_BF16: return run_sap<float, float, LNK_BF16R, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
         default: return set_error(QCD_EINVAL, "bad SAP storage precision");
     }
 }
