@@ -150,7 +150,7 @@ def fp64_single_rhs(fld, d, pos, npos, setup_s, little_maxit, log):
 
 KERNEL_SOURCES = {
     "k_sap_sweep": ["paper_1605_00564_amd/csrc/sap.hip", "paper_1605_00564_amd/csrc/internal.h"],
-    "k_dirac_rg": ["paper_1605_00564_amd/csrc/dirac.hip", "paper_1605_00564_amd/csrc/internal.h"],
+    "k_dirac": ["paper_1605_00564_amd/csrc/dirac.hip", "paper_1605_00564_amd/csrc/internal.h"],
 }
 
 
@@ -177,6 +177,14 @@ def measured_traffic(kernel, workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
+# stencil storage modes: (operator storage, spinor storage in and out)
+STENCIL_MODES = {
+    "f64": (F64, F64), "f32": (F32, F32),
+    "f16": (F16, F32), "bf16": (BF16, F32),         # FP16 / BF16 links and clover, FP32 spinors
+    "f16s": (F16, F16), "bf16s": (BF16, F16),       # the same with FP16 spinors (per-site scale)
+}
+
+
 def stencil_sweep(lattices, storages, nrhs_list, reps, log):
     """Dirac-operator GB/s and Gflop/s per storage mode and right-hand-side
     count (kernel time from HIP events; pack/unpack kernels excluded)."""
@@ -188,23 +196,24 @@ def stencil_sweep(lattices, storages, nrhs_list, reps, log):
         fld = dfl.Field(dims, (4, 4, 4, 4), 0.124, 1.5, torch.from_numpy(U).cuda())
         del U
         V = synth.volume(dims)
-        for st in storages:
+        for mode in storages:
+            st, sp = STENCIL_MODES[mode]
             dt = torch.complex128 if st == F64 else torch.complex64
             for n in nrhs_list:
                 x = torch.randn((n, V, 4, 3), dtype=dt, device="cuda")
                 y = torch.empty_like(x)
                 for _ in range(2):
-                    dfl.dirac_apply(fld, x, storage=st, out=y)
+                    dfl.dirac_apply(fld, x, storage=st, out=y, spinor_in=sp, spinor_out=sp)
                 torch.cuda.synchronize()
                 dfl.prof_reset()
                 dfl.prof_enable(True)
                 for _ in range(reps):
-                    dfl.dirac_apply(fld, x, storage=st, out=y)
+                    dfl.dirac_apply(fld, x, storage=st, out=y, spinor_in=sp, spinor_out=sp)
                 torch.cuda.synchronize()
                 dfl.prof_enable(False)
                 P = dfl.prof_get()["dirac"]
                 ms = P["ms"] / reps
-                row = {"lattice": "x".join(map(str, dims)), "storage": ["f64", "f32", "f16", "bf16"][st], "nrhs": n,
+                row = {"lattice": "x".join(map(str, dims)), "storage": mode, "nrhs": n,
                        "ms": ms, "GB/s": P["bytes"] / (P["ms"] * 1e-3) / 1e9,
                        "Gflop/s": P["flops"] / (P["ms"] * 1e-3) / 1e9,
                        "frac_hbm": P["bytes"] / (P["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS}
@@ -220,7 +229,8 @@ def main():
     ap.add_argument("--stencil-sweep", action="store_true",
                     help="only measure the Dirac stencil over storage modes and rhs counts")
     ap.add_argument("--sweep-lattices", default="32x16x16x16,64x32x32x32", help="T x X x Y x Z, comma separated")
-    ap.add_argument("--sweep-storage", default="0,1,2,3")
+    ap.add_argument("--sweep-storage", default="f64,f32,f16,bf16,f16s,bf16s",
+                    help="modes: " + ",".join(STENCIL_MODES))
     ap.add_argument("--sweep-nrhs", default="1,4,12,24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run five 1 GiB device copies (reference for hardware byte counters)")
@@ -268,7 +278,7 @@ def main():
         return
     if args.stencil_sweep:
         lats = [tuple(int(v) for v in s.split("x")) for s in args.sweep_lattices.split(",")]
-        rows = stencil_sweep(lats, [int(v) for v in args.sweep_storage.split(",")],
+        rows = stencil_sweep(lats, args.sweep_storage.split(","),
                              [int(v) for v in args.sweep_nrhs.split(",")], 10, log)
         print(json.dumps({"stencil_sweep": rows}), flush=True)
         return
@@ -365,7 +375,7 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = {"sap": "k_sap_sweep", "dirac": "k_dirac_rg", "blas": "vector algebra"}.get(dom, dom)
+    roof["kernel"] = {"sap": "k_sap_sweep", "dirac": "k_dirac", "blas": "vector algebra"}.get(dom, dom)
     roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
     roof["traffic_unit"] = "bytes per launch"
     roof["avg_launch_ms"] = avg_ms
@@ -379,7 +389,7 @@ def main():
                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "gflops": Pd["flops"] / (Pd["ms"] * 1e-3) / 1e9,
                    "avg_launch_ms": dms, "launches": Pd["launches"]}
         stencil["frac"] = stencil["achieved"] / PEAK_HBM_GBS
-        stencil["traffic"] = measured_traffic("k_dirac_rg", args.workload)
+        stencil["traffic"] = measured_traffic("k_dirac", args.workload)
         stencil["traffic_unit"] = "bytes per launch"
 
     infs, infe = state["infs"], state["infe"]

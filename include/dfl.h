@@ -102,6 +102,18 @@ int qcd_field_destroy(qcd_field f);
 int dirac_apply(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
                 hipStream_t stream);
 
+/* Same operator with explicit internal spinor storage on each side.
+ * spinor_in / spinor_out: QCD_F64 (with FP64 storage only), QCD_F32, or
+ * QCD_F16 = FP16 spinors with a per-site power-of-two scale (the site's
+ * largest |re| or |im| is scaled into [2^14, 2^15) before rounding; 52
+ * bytes per site), which needs QCD_F16 or QCD_BF16 operator storage.  The
+ * input is rounded to spinor_in on the way in and the result to spinor_out
+ * before it is returned; arithmetic is FP32 (FP64 with FP64 storage).
+ * dirac_apply(...) equals dirac_apply_ex(..., v, v) with v = F64 for FP64
+ * storage, else F32. */
+int dirac_apply_ex(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
+                   qcd_prec spinor_in, qcd_prec spinor_out, hipStream_t stream);
+
 /* Schwarz preconditioner psi = M_SAP eta (section 2.2): ncy cycles starting
  * from psi = 0; each cycle visits all blocks of colour 0 (Omega) in
  * parallel, then all blocks of colour 1 (Omega*).  A block visit computes the

@@ -82,6 +82,7 @@ def load():
     L.qcd_field_create_device.argtypes = [C.POINTER(_Lattice), P, P, C.POINTER(P)]
     L.qcd_field_destroy.argtypes = [P]
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
+    L.dirac_apply_ex.argtypes = [P, P, P, I, I, I, I, I, P]
     L.sap_precond.argtypes = [P, C.POINTER(_Sap), P, P, I, I, P]
     for name, args in [
         ("deflation_setup", [P, C.POINTER(_DflParams), P, C.POINTER(P)]),
@@ -301,13 +302,23 @@ class Deflation:
 # operations
 # ---------------------------------------------------------------------------
 
-def dirac_apply(field: Field, x, storage: int = F64, out=None):
-    """out = M x (kappa-normalised Wilson-clover operator)."""
+def dirac_apply(field: Field, x, storage: int = F64, out=None, spinor_in=None, spinor_out=None):
+    """out = M x (kappa-normalised Wilson-clover operator).  spinor_in /
+    spinor_out select the internal spinor storage on each side (F64, F32,
+    or F16 = FP16 with a per-site scale); by default F64 with FP64 storage,
+    else F32."""
     torch = _torch()
     n = _vec(x, field.V)
     out = torch.empty_like(x) if out is None else out
-    _check(load().dirac_apply(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _io_of(x),
-                              storage, _stream()), "dirac_apply")
+    if spinor_in is None and spinor_out is None:
+        _check(load().dirac_apply(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n,
+                                  _io_of(x), storage, _stream()), "dirac_apply")
+        return out
+    dflt = F64 if storage == F64 else F32
+    si = dflt if spinor_in is None else spinor_in
+    so = dflt if spinor_out is None else spinor_out
+    _check(load().dirac_apply_ex(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _io_of(x),
+                                 storage, si, so, _stream()), "dirac_apply_ex")
     return out
 
 

@@ -2,6 +2,7 @@
 // full lattice (both parities in one launch), multi right-hand side, and the
 // canonical <-> internal vector conversions.
 #include "internal.h"
+#include "blas.h"
 
 namespace dfl {
 
@@ -19,7 +20,7 @@ namespace dfl {
 // colour-major memory order), so that the blocks next to a tile, which hold
 // its off-block neighbours, are processed close by in time and on the same
 // XCD; without it they walk memory order.
-template <class S, class R, int LF, int CF, int RG>
+template <class S, class SO, class R, int LF, int CF, int RG>
 __global__ void __launch_bounds__(256) k_dirac_rg(const void *__restrict__ in, void *__restrict__ out,
                                                   const void *__restrict__ U, const void *__restrict__ clo,
                                                   const int *__restrict__ nbr, const int *__restrict__ border,
@@ -41,9 +42,8 @@ __global__ void __launch_bounds__(256) k_dirac_rg(const void *__restrict__ in, v
     const long x = (long)par * (V / 2) + pos;
     const int r = by * RG + sub;
     if (r >= nrhs) return;
-    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
-    const char *inb = static_cast<const char *>(in) + (size_t)r * fs;
-    char *outb = static_cast<char *>(out) + (size_t)r * fs;
+    const char *inb = static_cast<const char *>(in) + (size_t)r * Spin<S>::BYTES * V;
+    char *outb = static_cast<char *>(out) + (size_t)r * Spin<SO>::BYTES * V;
     cx<R> acc[12], w[9], p[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
@@ -57,6 +57,7 @@ __global__ void __launch_bounds__(256) k_dirac_rg(const void *__restrict__ in, v
         Link<LF>::load(U, V, MU, nb_index(eb), w);         \
         Spin<S>::load(inb, V, nb_index(eb), p);            \
         hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);      \
+        __builtin_amdgcn_sched_barrier(0);                 \
     }
     DFL_HOP_RG(0)
     DFL_HOP_RG(1)
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(256) k_dirac_rg(const void *__restrict__ in, v
     clover_apply<CF, R, true>(clo, V, x, p, o);
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = rmac(o[k], -kappa, acc[k]);
-    Spin<S>::store(outb, V, x, o);
+    Spin<SO>::store(outb, V, x, o);
 }
 
 // Block-staged stencil: one workgroup per (Schwarz block, right-hand side),
@@ -91,48 +92,65 @@ template <>
 struct Chunk<double> {
     using T = double2;
 };
+template <>
+struct Chunk<__half> {
+    using T = h8;
+};
 
+// one site's spinor from 16-byte chunks `stride` apart, through a generic
+// pointer (LDS or global memory); `sc` is the site's scale (FP16 storage)
 template <class S, class R>
-__device__ inline void lds_spin(const typename Chunk<S>::T *sm, int stride, int at, cx<R> v[12]) {
+__device__ inline void gen_spin(const typename Chunk<S>::T *src, long stride, const float *sc, cx<R> v[12]) {
     if constexpr (Spin<S>::NCH == 6) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const float4 t = sm[c * stride + at];
+            const float4 t = src[c * stride];
             v[2 * c] = {R(t.x), R(t.y)};
             v[2 * c + 1] = {R(t.z), R(t.w)};
         }
-    } else {
+    } else if constexpr (Spin<S>::NCH == 12) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const double2 t = sm[c * stride + at];
+            const double2 t = src[c * stride];
             v[c] = {R(t.x), R(t.y)};
         }
+    } else {
+        h8 t[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = src[c * stride];
+        Spin<__half>::decode(t, *sc, v);
     }
 }
 
-template <class S, class R, int LF, int CF, int MAXT>
+// RES: out = b - M in, and the workgroup's share of ||out||^2 into
+// part[rhs][block] (a fixed order of additions, so the norm is reproducible).
+// S: input spinor storage (staged in LDS), SO: output storage.
+template <class S, class SO, class R, int LF, int CF, int MAXT, bool RES = false>
 __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in, void *__restrict__ out,
                                                     const void *__restrict__ U, const void *__restrict__ clo,
                                                     const int *__restrict__ nbr, const short *__restrict__ lnbr,
                                                     const int *__restrict__ border, long V, long Vh, int Vbh,
-                                                    R kappa) {
+                                                    R kappa, const void *__restrict__ b = nullptr,
+                                                    double *__restrict__ part = nullptr) {
     using T = typename Chunk<S>::T;
     constexpr int NCH = Spin<S>::NCH;
+    constexpr bool HALF = NCH == 3;
     extern __shared__ unsigned char dsm_raw[];
-    T *sm = reinterpret_cast<T *>(dsm_raw);
     unsigned bx, r;
     xcd_order(bx, r);
     const long B = border[bx];
     const int Vb = 2 * Vbh;
+    T *sm = reinterpret_cast<T *>(dsm_raw);
+    float *smsc = reinterpret_cast<float *>(sm + NCH * Vb);  // per-site scales (FP16 storage)
     const int t = threadIdx.x;
     const int par = t >= Vbh ? 1 : 0;
     const int j = t - par * Vbh;
     const unsigned x = (unsigned)(par * Vh + B * Vbh + j);
-    const size_t fs = (size_t)NCH * V * 16;
-    const char *inb = wave_uniform(static_cast<const char *>(in) + (size_t)r * fs);
-    char *outb = wave_uniform(static_cast<char *>(out) + (size_t)r * fs);
+    const char *inb = wave_uniform(static_cast<const char *>(in) + (size_t)r * Spin<S>::BYTES * V);
+    char *outb = wave_uniform(static_cast<char *>(out) + (size_t)r * Spin<SO>::BYTES * V);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) sm[c * Vb + t] = ld<T>(inb, c, V, x);
+    if constexpr (HALF) smsc[t] = ld<float>(inb, 12, V, x);
     __syncthreads();
     const uint4 nb4 = ld<uint4>(lnbr, 0, 0, (unsigned)t);
     const unsigned nbw[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
@@ -140,42 +158,34 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
     cx<R> acc[12], w[9], p[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
-    // Neighbour spinor through a generic pointer: LDS inside the block,
+    // Each hop ends in a scheduling fence: without it the compiler hoists
+    // all 48 neighbour loads to the top and keeps them live (up to 250
+    // registers).  Neighbour spinor through a generic pointer: LDS inside the block,
     // global memory outside, one flat load per chunk and no divergent branch.
     // The neighbour table is read for every hop (in-block entries carry the
     // right index and no boundary sign): a load guarded by the in-block test
     // becomes a branch that costs far more registers than the table read.
     const T *sm_g = sm;
     const T *in_g = reinterpret_cast<const T *>(inb);
-    auto flat_spin = [&](const T *src, long stride, cx<R> v[12]) {
-        if constexpr (NCH == 6) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const float4 q = src[c * stride];
-                v[2 * c] = {R(q.x), R(q.y)};
-                v[2 * c + 1] = {R(q.z), R(q.w)};
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const double2 q = src[c * stride];
-                v[c] = {R(q.x), R(q.y)};
-            }
-        }
-    };
-#define DFL_BLK_HOP(MU)                                                                  \
-    {                                                                                    \
-        const int lf = (short)(nbw[MU] & 0xffffu);                                       \
-        const int lb = (short)(nbw[MU] >> 16);                                           \
-        const int ef = nbr_at(nbr, 2 * MU, V, x);                                        \
-        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);                                    \
-        Link<LF>::load(U, V, MU, x, w);                                                  \
-        flat_spin(lf >= 0 ? sm_g + obase + lf : in_g + nb_index(ef), lf >= 0 ? Vb : V, p); \
-        hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);                                     \
-        const unsigned y = nb_index(eb);                                                 \
-        flat_spin(lb >= 0 ? sm_g + obase + lb : in_g + y, lb >= 0 ? Vb : V, p);          \
-        Link<LF>::load(U, V, MU, y, w);                                                  \
-        hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);                                    \
+    const float *smsc_g = smsc;
+    const float *insc_g = reinterpret_cast<const float *>(inb) + 12 * V;
+#define DFL_BLK_HOP(MU)                                                                                 \
+    {                                                                                                   \
+        const int lf = (short)(nbw[MU] & 0xffffu);                                                      \
+        const int lb = (short)(nbw[MU] >> 16);                                                          \
+        const int ef = nbr_at(nbr, 2 * MU, V, x);                                                       \
+        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);                                                   \
+        Link<LF>::load(U, V, MU, x, w);                                                                 \
+        const unsigned yf = nb_index(ef);                                                               \
+        gen_spin<S, R>(lf >= 0 ? sm_g + obase + lf : in_g + yf, lf >= 0 ? Vb : V,                       \
+                       lf >= 0 ? smsc_g + obase + lf : insc_g + yf, p);                                 \
+        hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);                                                    \
+        const unsigned y = nb_index(eb);                                                                \
+        gen_spin<S, R>(lb >= 0 ? sm_g + obase + lb : in_g + y, lb >= 0 ? Vb : V,                        \
+                       lb >= 0 ? smsc_g + obase + lb : insc_g + y, p);                                  \
+        Link<LF>::load(U, V, MU, y, w);                                                                 \
+        hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);                                                   \
+        __builtin_amdgcn_sched_barrier(0);                                                              \
     }
     DFL_BLK_HOP(0)
     DFL_BLK_HOP(1)
@@ -183,14 +193,33 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
     DFL_BLK_HOP(3)
 #undef DFL_BLK_HOP
     cx<R> o[12];
-    lds_spin<S, R>(sm, Vb, t, p);
+    gen_spin<S, R>(sm_g + t, Vb, smsc_g + t, p);
     clover_apply<CF, R, true>(clo, V, x, p, o);
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = rmac(o[k], -kappa, acc[k]);
-    Spin<S>::store(outb, V, x, o);
+    if constexpr (RES) {
+        __shared__ double red[MAXT / 64];
+        Spin<S>::load(wave_uniform(static_cast<const char *>(b) + (size_t)r * Spin<S>::BYTES * V), V, x, p);
+        double nn = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o[k] = p[k] - o[k];
+            nn = ffma((double)o[k].re, (double)o[k].re, ffma((double)o[k].im, (double)o[k].im, nn));
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+        if ((t & 63) == 0) red[t >> 6] = nn;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0;
+            for (int w = 0; w < (Vb + 63) / 64; ++w) sum += red[w];
+            part[(size_t)r * gridDim.x + bx] = sum;
+        }
+    }
+    Spin<SO>::store(outb, V, x, o);
 }
 
-template <class S, class R, int LF, int CF>
+template <class S, class SO, class R, int LF, int CF>
 static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStream_t s) {
     const long V = f->g.V;
     const R kappa = (R)f->lat.kappa;
@@ -201,7 +230,7 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     // bytes = 4 links + clover per site once, spinor in + out per rhs
     const double lbytes = LF == LNK_F64 ? 144 : LF == LNK_F32 ? 48 : 24;
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
-    const double sbytes = 2.0 * 24 * sizeof(S);
+    const double sbytes = (double)Spin<S>::BYTES + Spin<SO>::BYTES;
     auto work = [&](int n) { return std::make_tuple(1872.0 * V * n, V * (4 * lbytes + cbytes + n * sbytes), 1.0 * V * n); };
     // right-hand sides per site group (tuning knob; 0 = automatic)
     static const int rg_env = [] {
@@ -224,12 +253,12 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
         return e ? atoi(e) : 1;
     }();
     const int Vb = 2 * f->g.Vbh;
-    const size_t lds = (size_t)Spin<S>::NCH * Vb * 16;
-    if (blk_env && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(S) == 4)) {
+    const size_t lds = (size_t)Spin<S>::BYTES * Vb;
+    if (blk_env && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(R) == 4)) {
         const dim3 grid((unsigned)f->g.Nb, (unsigned)nrhs);
 #define DFL_BLK_LAUNCH(MAXT)                                                                                  \
-    k_dirac_blk<S, R, LF, CF, MAXT><<<grid, Vb, lds, s>>>(in, out, U, C, f->nbr, f->lnbr, f->border, V, f->g.Vh, \
-                                                          f->g.Vbh, kappa)
+    k_dirac_blk<S, SO, R, LF, CF, MAXT><<<grid, Vb, lds, s>>>(in, out, U, C, f->nbr, f->lnbr, f->border, V,      \
+                                                              f->g.Vh, f->g.Vbh, kappa)
         if (Vb <= 256) DFL_BLK_LAUNCH(256);
         else if (Vb <= 512) DFL_BLK_LAUNCH(512);
         else DFL_BLK_LAUNCH(1024);
@@ -239,7 +268,7 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     }
     // grid: (V / 2) / tile site tiles x ceil(nrhs / RG) groups; V/2 is a multiple of 128
 #define DFL_RG_LAUNCH(RGV)                                                                            \
-    k_dirac_rg<S, R, LF, CF, RGV><<<dim3((unsigned)(V / 2 / (BS / (2 * RGV))), (nrhs + RGV - 1) / RGV), BS, 0, s>>>( \
+    k_dirac_rg<S, SO, R, LF, CF, RGV><<<dim3((unsigned)(V / 2 / (BS / (2 * RGV))), (nrhs + RGV - 1) / RGV), BS, 0, s>>>( \
         in, out, U, C, f->nbr, border, V, f->g.Vbh, kappa, nrhs)
     switch (rg) {
         case 2: DFL_RG_LAUNCH(2); break;
@@ -251,19 +280,76 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     return 0;
 }
 
+int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int nrhs, double *norm2,
+                hipStream_t s) {
+    const Geom &g = f->g;
+    const int Vb = 2 * g.Vbh;
+    const size_t lds = (size_t)12 * Vb * 16;
+    if (!(Vb % 64 == 0 && Vb <= 512 && lds <= 64 * 1024)) {
+        // blocks that do not fit one workgroup: stencil, then a separate pass
+        const size_t tb = sizeof(double2) * 12 * g.V * nrhs;
+        void *tp;
+        DFL_TRY(field_buffer(f, BUF_RES, tb + sizeof(double) * (size_t)nrhs * BLAS_NBLK, &tp));
+        double2 *t = static_cast<double2 *>(tp);
+        DFL_TRY(dirac_internal(f, x, t, nrhs, QCD_F64, QCD_F64, s));
+        return blas_resid(b, t, r, 12 * g.V, nrhs, reinterpret_cast<double *>(static_cast<char *>(tp) + tb), norm2,
+                          s);
+    }
+    void *pp;
+    DFL_TRY(field_buffer(f, BUF_RES, sizeof(double) * (size_t)nrhs * g.Nb, &pp));
+    double *part = static_cast<double *>(pp);
+    {
+        // 1872 flop per site (+ 2 x 24 for the difference and the norm);
+        // bytes: FP64 links and clover once, x, b in and r out per rhs
+        ProfScope ps(PROF_DIRAC, s, 1920.0 * g.V * nrhs, g.V * (4 * 144.0 + 576.0 + nrhs * 3 * 192.0),
+                     1.0 * g.V * nrhs);
+        const dim3 grid((unsigned)g.Nb, (unsigned)nrhs);
+        if (Vb <= 256)
+            k_dirac_blk<double, double, double, LNK_F64, CLO_F64, 256, true><<<grid, Vb, lds, s>>>(
+                x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh,
+                f->lat.kappa, b, part);
+        else
+            k_dirac_blk<double, double, double, LNK_F64, CLO_F64, 512, true><<<grid, Vb, lds, s>>>(
+                x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh,
+                f->lat.kappa, b, part);
+        DFL_HIP(hipGetLastError());
+    }
+    return blas_reduce(part, 1, g.Nb, nrhs, norm2, s);
+}
+
+// vin / vout: internal vector storage of input and output (F64, F32, or
+// F16 = FP16 with per-site scale); FP16 vectors need FP16/BF16 operator
+// storage, FP64 vectors FP64 storage
+int dirac_internal2(qcd_field f, const void *in, qcd_prec vin, void *out, qcd_prec vout, int nrhs,
+                    qcd_prec storage, hipStream_t s) {
+    if (vin == QCD_F64 || vout == QCD_F64) {
+        if (vin != vout || storage != QCD_F64)
+            return set_error(QCD_EINVAL, "FP64 vectors need FP64 operator storage on both sides");
+        return launch_dirac<double, double, double, LNK_F64, CLO_F64>(f, in, out, nrhs, s);
+    }
+    if (vin == QCD_F16 && storage != QCD_F16 && storage != QCD_BF16)
+        return set_error(QCD_EINVAL, "FP16 spinors need FP16 or BF16 operator storage");
+#define DFL_DIRAC_IO(LF, CF)                                                                        \
+    if (vin == QCD_F32 && vout == QCD_F32) return launch_dirac<float, float, float, LF, CF>(f, in, out, nrhs, s);    \
+    if (vin == QCD_F16 && vout == QCD_F32) return launch_dirac<__half, float, float, LF, CF>(f, in, out, nrhs, s);  \
+    if (vin == QCD_F16 && vout == QCD_F16) return launch_dirac<__half, __half, float, LF, CF>(f, in, out, nrhs, s); \
+    if (vin == QCD_F32 && vout == QCD_F16) return launch_dirac<float, __half, float, LF, CF>(f, in, out, nrhs, s);  \
+    return set_error(QCD_EINVAL, "vector precision must be F64, F32 or F16");
+    switch (storage) {
+        case QCD_F32: {
+            if (vin == QCD_F16 || vout == QCD_F16) return set_error(QCD_EINVAL, "FP16 spinors need FP16/BF16 storage");
+            return launch_dirac<float, float, float, LNK_F32, CLO_F32>(f, in, out, nrhs, s);
+        }
+        case QCD_F16: { DFL_DIRAC_IO(LNK_F16, CLO_F16) }
+        case QCD_BF16: { DFL_DIRAC_IO(LNK_BF16, CLO_F16) }
+        default: return set_error(QCD_EINVAL, "FP32 and FP16 vectors take F32, F16 or BF16 operator storage");
+    }
+#undef DFL_DIRAC_IO
+}
+
 int dirac_internal(qcd_field f, const void *in, void *out, int nrhs, qcd_prec vec, qcd_prec storage,
                    hipStream_t s) {
-    if (vec == QCD_F64) {
-        if (storage != QCD_F64) return set_error(QCD_EINVAL, "FP64 vectors need FP64 operator storage");
-        return launch_dirac<double, double, LNK_F64, CLO_F64>(f, in, out, nrhs, s);
-    }
-    if (vec != QCD_F32) return set_error(QCD_EINVAL, "vector precision must be F64 or F32");
-    switch (storage) {
-        case QCD_F32: return launch_dirac<float, float, LNK_F32, CLO_F32>(f, in, out, nrhs, s);
-        case QCD_F16: return launch_dirac<float, float, LNK_F16, CLO_F16>(f, in, out, nrhs, s);
-        case QCD_BF16: return launch_dirac<float, float, LNK_BF16, CLO_F16>(f, in, out, nrhs, s);
-        default: return set_error(QCD_EINVAL, "FP32 vectors take F32, F16 or BF16 operator storage");
-    }
+    return dirac_internal2(f, in, vec, out, vec, nrhs, storage, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,7 +366,7 @@ __global__ void k_pack(const CT *__restrict__ canon, void *__restrict__ out, con
     cx<R> v[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = {src[k].x, src[k].y};
-    Spin<S>::store(static_cast<char *>(out) + (size_t)r * Spin<S>::NCH * V * 16, V, idx, v);
+    Spin<S>::store(static_cast<char *>(out) + (size_t)r * Spin<S>::BYTES * V, V, idx, v);
 }
 
 template <class CT, class S>
@@ -291,7 +377,7 @@ __global__ void k_unpack(const void *__restrict__ in, CT *__restrict__ canon, co
     const int r = blockIdx.y;
     using R = decltype(CT::x);
     cx<R> v[12];
-    Spin<S>::load(static_cast<const char *>(in) + (size_t)r * Spin<S>::NCH * V * 16, V, idx, v);
+    Spin<S>::load(static_cast<const char *>(in) + (size_t)r * Spin<S>::BYTES * V, V, idx, v);
     CT *dst = canon + ((size_t)r * V + lex_of[idx]) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -313,6 +399,10 @@ int pack_spinor(qcd_field f, const void *canon, qcd_prec io, void *internal, qcd
         k_pack<float2, float><<<grid, 256, 0, s>>>((const float2 *)canon, internal, f->lex_of, V);
     else if (io == QCD_F32 && vec == QCD_F64)
         k_pack<float2, double><<<grid, 256, 0, s>>>((const float2 *)canon, internal, f->lex_of, V);
+    else if (io == QCD_F32 && vec == QCD_F16)
+        k_pack<float2, __half><<<grid, 256, 0, s>>>((const float2 *)canon, internal, f->lex_of, V);
+    else if (io == QCD_F64 && vec == QCD_F16)
+        k_pack<double2, __half><<<grid, 256, 0, s>>>((const double2 *)canon, internal, f->lex_of, V);
     else
         return set_error(QCD_EINVAL, "io precision must be F64 or F32");
     DFL_HIP(hipGetLastError());
@@ -332,6 +422,10 @@ int unpack_spinor(qcd_field f, const void *internal, qcd_prec vec, void *canon, 
         k_unpack<float2, float><<<grid, 256, 0, s>>>(internal, (float2 *)canon, f->lex_of, V);
     else if (io == QCD_F32 && vec == QCD_F64)
         k_unpack<float2, double><<<grid, 256, 0, s>>>(internal, (float2 *)canon, f->lex_of, V);
+    else if (io == QCD_F32 && vec == QCD_F16)
+        k_unpack<float2, __half><<<grid, 256, 0, s>>>(internal, (float2 *)canon, f->lex_of, V);
+    else if (io == QCD_F64 && vec == QCD_F16)
+        k_unpack<double2, __half><<<grid, 256, 0, s>>>(internal, (double2 *)canon, f->lex_of, V);
     else
         return set_error(QCD_EINVAL, "io precision must be F64 or F32");
     DFL_HIP(hipGetLastError());
@@ -342,18 +436,26 @@ int unpack_spinor(qcd_field f, const void *internal, qcd_prec vec, void *canon, 
 
 using namespace dfl;
 
-extern "C" int dirac_apply(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
-                           hipStream_t s) {
+extern "C" int dirac_apply_ex(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
+                              qcd_prec spinor_in, qcd_prec spinor_out, hipStream_t s) {
     if (!f || !in || !out || nrhs <= 0) return set_error(QCD_EINVAL, "bad arguments to dirac_apply");
     if (io != QCD_F64 && io != QCD_F32) return set_error(QCD_EINVAL, "io precision must be F64 or F32");
     if (in == out) return set_error(QCD_EINVAL, "dirac_apply: in and out must differ");
-    const qcd_prec vec = storage == QCD_F64 ? QCD_F64 : QCD_F32;
-    const size_t nb = spinor_bytes(vec, f->g.V) * nrhs;
+    for (qcd_prec v : {spinor_in, spinor_out})
+        if (v != QCD_F64 && v != QCD_F32 && v != QCD_F16)
+            return set_error(QCD_EINVAL, "spinor storage must be F64, F32 or F16");
+    const size_t na = spinor_bytes(spinor_in, f->g.V) * nrhs, nb = spinor_bytes(spinor_out, f->g.V) * nrhs;
     void *ws;
-    DFL_TRY(field_buffer(f, BUF_APPLY, 2 * nb, &ws));
-    char *a = static_cast<char *>(ws), *b = a + nb;
-    DFL_TRY(pack_spinor(f, in, io, a, vec, nrhs, s));
-    DFL_TRY(dirac_internal(f, a, b, nrhs, vec, storage, s));
-    DFL_TRY(unpack_spinor(f, b, vec, out, io, nrhs, s));
+    DFL_TRY(field_buffer(f, BUF_APPLY, na + nb, &ws));
+    char *a = static_cast<char *>(ws), *b = a + na;
+    DFL_TRY(pack_spinor(f, in, io, a, spinor_in, nrhs, s));
+    DFL_TRY(dirac_internal2(f, a, spinor_in, b, spinor_out, nrhs, storage, s));
+    DFL_TRY(unpack_spinor(f, b, spinor_out, out, io, nrhs, s));
     return 0;
+}
+
+extern "C" int dirac_apply(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
+                           hipStream_t s) {
+    const qcd_prec vec = storage == QCD_F64 ? QCD_F64 : QCD_F32;
+    return dirac_apply_ex(f, in, out, nrhs, io, storage, vec, vec, s);
 }

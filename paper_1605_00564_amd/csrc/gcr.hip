@@ -64,16 +64,15 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     const qcd_prec opst = vin == QCD_F64 ? QCD_F64 : (p->sap.storage == QCD_F64 ? QCD_F32 : p->sap.storage);
     const size_t vbytes = sizeof(E) * ne;  // one rhs
 
-    // work space: Z[nkv][n], W[nkv][n], rho[n], tmp[n] (inner); r, t (FP64)
+    // work space: Z[nkv][n], W[nkv][n], rho[n], tmp[n] (inner); r (FP64)
     void *wp, *wio;
     DFL_TRY(field_buffer(f, BUF_GCR, vbytes * n * (2 * (size_t)nkv + 2), &wp));
-    DFL_TRY(field_buffer(f, BUF_GCR_IO, sizeof(double2) * ne64 * n * 2, &wio));
+    DFL_TRY(field_buffer(f, BUF_GCR_IO, sizeof(double2) * ne64 * n, &wio));
     E *Z = static_cast<E *>(wp);
     E *W = Z + (size_t)nkv * n * ne;
     E *rho = W + (size_t)nkv * n * ne;
     E *tmp = rho + (size_t)n * ne;
     double2 *r = static_cast<double2 *>(wio);
-    double2 *t = r + (size_t)n * ne64;
     Scal sc;
     void *sp;
     DFL_TRY(field_buffer(f, BUF_RED, scalar_bytes(n), &sp));
@@ -100,8 +99,7 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     // is removed here, in FP64, before the next cycle.
     auto low_mode_correction = [&]() -> int {
         DFL_TRY(dfl_low_mode(p->dfl, r, x, n, p->little_tol, std::max(p->little_maxit, 200), s));
-        DFL_TRY(dirac_internal(f, x, t, n, QCD_F64, QCD_F64, s));
-        DFL_TRY(blas_resid(b, t, r, ne64, n, sc.part, sc.red, s));
+        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
         DFL_TRY(fetch(f, sc.red, n, s, h));
         for (int i = 0; i < n; ++i) rn[i] = std::sqrt(h[i]);
         return 0;
@@ -156,8 +154,7 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         }
         DFL_TRY(gcr_trisolve(sc.R, sc.cvec, n, k, sc.alpha, s));
         DFL_TRY(accum(x, Z, V, n, k, sc.alpha, s));
-        DFL_TRY(dirac_internal(f, x, t, n, QCD_F64, QCD_F64, s));
-        DFL_TRY(blas_resid(b, t, r, ne64, n, sc.part, sc.red, s));
+        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
         DFL_TRY(fetch(f, sc.red, n, s, h));
         for (int i = 0; i < n; ++i) {
             if (!std::isfinite(h[i])) return set_error(QCD_ENAN, "NaN in the recomputed residual");

@@ -187,7 +187,8 @@ template <class S>
 struct Spin;
 template <>
 struct Spin<double> {
-    static constexpr int NCH = 12;
+    static constexpr int NCH = 12;   // 16-byte chunks per site
+    static constexpr int BYTES = 192;  // bytes per site
     template <class R>
     __device__ static inline void load(const void *base, long V, unsigned idx, cx<R> v[12]) {
 #pragma unroll
@@ -205,6 +206,7 @@ struct Spin<double> {
 template <>
 struct Spin<float> {
     static constexpr int NCH = 6;
+    static constexpr int BYTES = 96;
     template <class R>
     __device__ static inline void load(const void *base, long V, unsigned idx, cx<R> v[12]) {
 #pragma unroll
@@ -224,8 +226,60 @@ struct Spin<float> {
     }
 };
 
-// bytes of one spinor (one RHS) in each storage type
-inline size_t spinor_bytes(qcd_prec p, long V) { return (p == QCD_F64 ? 192 : 96) * (size_t)V; }
+// FP16 spinor with a per-site power-of-two scale: a right-hand side holds
+// 3 chunks of [V] x 8 halves (4 complex each), then [V] FP32 scales (52 V
+// bytes).  The scale 2^e puts the site's largest |re| or |im| in
+// [2^14, 2^15) before rounding, so every site keeps FP16's full relative
+// precision whatever the field's dynamic range, and the scaling is exact.
+template <>
+struct Spin<__half> {
+    static constexpr int NCH = 3;
+    static constexpr int BYTES = 52;
+    template <class R>
+    __device__ static inline void decode(const h8 t[3], float sc, cx<R> v[12]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[4 * c + e] = {R(__half2float(t[c].v[2 * e]) * sc), R(__half2float(t[c].v[2 * e + 1]) * sc)};
+    }
+    template <class R>
+    __device__ static inline void load(const void *base, long V, unsigned idx, cx<R> v[12]) {
+        h8 t[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = ld<h8>(base, c, V, idx);
+        decode(t, ld<float>(base, 12, V, idx), v);
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long V, unsigned idx, const cx<R> v[12]) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(float(v[k].re)), fabsf(float(v[k].im))));
+        // m = f 2^e with f in [0.5, 1): e = biased exponent - 126.  Scale
+        // 2^(e-15) and its inverse are built from exponent bits; sites whose
+        // largest entry is below 2^-112 are stored as zero.
+        const int eb = (int)((__float_as_uint(m) >> 23) & 0xffu);
+        const bool nz = eb >= 15;
+        const float sc = nz ? __uint_as_float((unsigned)(eb - 14) << 23) : 0.f;
+        const float inv = nz ? __uint_as_float((unsigned)(268 - eb) << 23) : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h8 t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                t.v[2 * q] = __float2half_rn(float(v[4 * c + q].re) * inv);
+                t.v[2 * q + 1] = __float2half_rn(float(v[4 * c + q].im) * inv);
+            }
+            st<h8>(base, c, V, idx, t);
+        }
+        st<float>(base, 12, V, idx, sc);
+    }
+};
+
+// bytes of one spinor (one RHS) in each storage type (F16 = FP16 with scale)
+inline size_t spinor_bytes(qcd_prec p, long V) {
+    return (p == QCD_F64 ? 192 : p == QCD_F16 ? 52 : 96) * (size_t)V;
+}
 
 // Link access: 3x3 matrix W of site idx and direction mu.
 template <int F>
@@ -538,8 +592,8 @@ struct qcd_field_s {
     void *clo[3] = {nullptr, nullptr, nullptr};             // by CloFmt, all sites
     void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
     // scratch buffers owned by the handle, one per purpose, grown on demand
-    void *buf[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t buf_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    void *buf[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t buf_bytes[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
     double *hp = nullptr;    // pinned host scratch (4096 doubles)
 };
@@ -547,7 +601,10 @@ struct qcd_field_s {
 namespace dfl {
 
 // grow-only device scratch of a field handle, one buffer per purpose
-enum BufSlot { BUF_APPLY = 0, BUF_SAP = 1, BUF_GCR = 2, BUF_GCR_IO = 3, BUF_DFL = 4, BUF_AMA = 5, BUF_RED = 6, BUF_SAP_IO = 7 };
+enum BufSlot {
+    BUF_APPLY = 0, BUF_SAP = 1, BUF_GCR = 2, BUF_GCR_IO = 3, BUF_DFL = 4, BUF_AMA = 5, BUF_RED = 6, BUF_SAP_IO = 7,
+    BUF_RES = 8
+};
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
 
 // Profiling of kernel classes with HIP events.
@@ -571,6 +628,12 @@ inline CloFmt clo_fmt(qcd_prec p) { return p == QCD_F64 ? CLO_F64 : p == QCD_F32
 
 // --- internal operations (device pointers in the internal layout) ---------
 // out = M in on internal vectors; nrhs fields of type S (double or float)
+// r = b - M x with the FP64 operator and ||r||^2 per right-hand side into
+// `norm2` (device, n doubles); internal FP64 vectors
+int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int nrhs, double *norm2,
+                hipStream_t s);
+int dirac_internal2(qcd_field f, const void *in, qcd_prec vin, void *out, qcd_prec vout, int nrhs,
+                    qcd_prec storage, hipStream_t s);
 int dirac_internal(qcd_field f, const void *in, void *out, int nrhs, qcd_prec vec, qcd_prec storage,
                    hipStream_t s);
 // psi = M_SAP eta on internal vectors (FP32 vectors unless sap.storage == F64)

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(MAXT)
     const int tid = threadIdx.x;
     unsigned bx, rhs;
     xcd_order(bx, rhs);
-    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
+    const size_t fs = (size_t)Spin<S>::BYTES * V;
     const void *eta = wave_uniform(static_cast<const char *>(eta_all) + rhs * fs);
     void *psi = wave_uniform(static_cast<char *>(psi_all) + rhs * fs);
     const long B = (long)colour * nbc + bx;
@@ -280,7 +280,7 @@ __global__ void k_zero_colour(void *psi_all, long V, long Vh, long half, long cs
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * half) return;
     const long idx = (t < half ? 0 : Vh) + cstart + (t < half ? t : t - half);
-    const size_t fs = (size_t)Spin<S>::NCH * V * 16;
+    const size_t fs = (size_t)Spin<S>::BYTES * V;
     cx<float> z[12];
     for (int c = 0; c < 12; ++c) z[c] = {0.f, 0.f};
     Spin<S>::store(static_cast<char *>(psi_all) + blockIdx.y * fs, V, idx, z);
@@ -331,7 +331,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
             const int first = (cy == 0 && col == 0) ? 1 : 0;
             dim3 grid(nbc, nrhs);
             const double fl = pairs * ((first ? 0.0 : 3792.0) + 504 + (h + 72) + nmr * (2 * h + 1392) + (h + 576));
-            const double by = pairs * (2 * 24 * sizeof(S) * (first ? 2 : 3)) + (double)nbc * Vbh * 2 *
+            const double by = pairs * (2.0 * Spin<S>::BYTES * (first ? 2 : 3)) + (double)nbc * Vbh * 2 *
                               (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
             ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
 #define DFL_SAP_LAUNCH(LDSV, KSV, MAXT)                                                                        \

@@ -60,5 +60,26 @@ def quantise_clover(Am: np.ndarray, kind: str) -> np.ndarray:
     return out
 
 
+def quantise_spinor_f16(x: np.ndarray) -> np.ndarray:
+    """FP16 spinor storage with a per-site power-of-two scale: per site the
+    largest |re| or |im| m (taken in FP32) = f 2^e with f in [0.5, 1); the
+    site is divided by 2^(e - 15), rounded to FP16 (round to nearest even)
+    and multiplied back.  Sites with m < 2^-112 are stored as zero.  Input
+    [..., V, 4, 3] complex; the scaling is exact, so this reproduces the
+    stored values bit for bit."""
+    z = np.asarray(x).astype(np.complex64)
+    shp = z.shape
+    re = z.real.reshape(shp[:-2] + (12,))
+    im = z.imag.reshape(shp[:-2] + (12,))
+    m = np.maximum(np.abs(re).max(axis=-1), np.abs(im).max(axis=-1)).astype(np.float32)
+    _, e = np.frexp(m)
+    nz = m >= np.float32(2.0 ** -112)
+    sc = np.where(nz, np.ldexp(np.float32(1.0), (e - 15)).astype(np.float32), np.float32(0.0))
+    inv = np.where(nz, np.ldexp(np.float32(1.0), (15 - e)).astype(np.float32), np.float32(0.0))
+    qr = (re * inv[..., None]).astype(np.float16).astype(np.float32) * sc[..., None]
+    qi = (im * inv[..., None]).astype(np.float16).astype(np.float32) * sc[..., None]
+    return (qr.astype(np.float64) + 1j * qi.astype(np.float64)).reshape(shp)
+
+
 STORAGE_KIND = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
 CLOVER_KIND = {0: "f64", 1: "f32", 2: "f16", 3: "f16"}

@@ -91,6 +91,47 @@ def test_dirac_reduced_precision_matches_quantised_oracle(key, storage):
     assert rel(y[0], unq[0]) < {F32: 1e-6, F16: 3e-3, BF16: 2e-2}[storage]
 
 
+@pytest.mark.parametrize("storage", [F16, BF16])
+@pytest.mark.parametrize("key", [SMALL, MID])
+def test_dirac_fp16_spinors_match_quantised_oracle(key, storage):
+    """FP16 spinor storage with a per-site power-of-two scale.  Input side:
+    the oracle applies the same operator to the identically quantised input
+    (tests/quant.py reproduces the stored values bit for bit), compared
+    before any output rounding (FP32 output): 1e-5.  Output side: the FP16
+    output is the same FP32 arithmetic stored in the FP16 format, so it must
+    equal the format's encoding of the FP32 output (reproduced bit for bit
+    by tests/quant.py) up to isolated one-ulp flips where the two kernels'
+    FP32 results straddle an FP16 rounding boundary.  The small lattice uses
+    2^4 blocks (site-tile kernel), the other 4^4 blocks (block-staged
+    kernel); the batch spans 12 right-hand sides with a dynamic range of
+    10^6 between sites."""
+    torch, dfl = _gpu()
+    c = case(*key)
+    x = synth.gaussian_spinor(c.dims, 12, 1005)
+    x = x * np.exp(np.linspace(-7.0, 7.0, x.shape[1]))[None, :, None, None]
+    x = x.astype(np.complex64)
+    xq = quant.quantise_spinor_f16(x)
+    xt = torch.from_numpy(x).cuda()
+    y32 = dfl.dirac_apply(c.field, xt, storage=storage, spinor_in=F16, spinor_out=F32).cpu().numpy()
+    y16 = dfl.dirac_apply(c.field, xt, storage=storage, spinor_in=F16, spinor_out=F16).cpu().numpy()
+    q = c.qop(storage)
+    for r in (0, 5, 11):
+        ref = q.M(xq[r])
+        err = rel(y32[r], ref)
+        print("fp16 spinors, storage", storage, "rhs", r, "rel err (fp32 out)", err)
+        assert err <= 1e-5
+        enc = quant.quantise_spinor_f16(y32[r])
+        differ = float(np.mean(enc != y16[r]))
+        m = np.maximum(np.abs(enc.real), np.abs(enc.imag)).reshape(enc.shape[0], -1).max(axis=1)
+        dd = y16[r] - enc
+        d = np.maximum(np.abs(dd.real), np.abs(dd.imag)).reshape(enc.shape[0], -1).max(axis=1)
+        worst = float(np.max(d / np.maximum(m, 1e-300)))
+        print("fp16 spinors, storage", storage, "rhs", r, "fp16 out vs encoded fp32 out: differing fraction",
+              differ, "worst per-site deviation / site max", worst)
+        assert differ < 1e-3
+        assert worst <= 2.0 ** -10
+
+
 @pytest.mark.parametrize("key", [SMALL, MID])
 def test_sap_fp64_matches_oracle(key):
     torch, dfl = _gpu()
