@@ -109,7 +109,7 @@ def cpu_baseline(work, block, prof, nsrc, ncy, nmr, threads):
     }
 
 
-def fp64_single_rhs(fld, d, pos, npos, setup_s, little_maxit, log):
+def fp64_single_rhs(fld, d, pos, npos, setup_s, little_maxit, little_maxit_sloppy, log):
     """The comparator: the same deflated SAP-GCR solver with every step in
     FP64 (operator storage, Schwarz sweeps, Krylov vectors) and one
     right-hand side per solve, at the same final residuals.  Timed on a
@@ -119,7 +119,7 @@ def fp64_single_rhs(fld, d, pos, npos, setup_s, little_maxit, log):
     import torch
     import paper_1605_00564_amd as dfl
     sap = dfl.SapParams(5, 4, F64)
-    sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sap, dfl=d, little_tol=1e-6, little_maxit=little_maxit)
+    sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sap, dfl=d, little_tol=1e-6, little_maxit=little_maxit_sloppy)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap, dfl=d, little_tol=1e-10, little_maxit=little_maxit)
     V = fld.V
     xs = [torch.empty((12, V, 4, 3), dtype=torch.complex128, device="cuda")]
@@ -244,7 +244,10 @@ def main():
     ap.add_argument("--no-deflation", action="store_true")
     ap.add_argument("--sloppy-storage", type=int, default=F16)
     ap.add_argument("--batch", type=int, default=0)
-    ap.add_argument("--little-maxit", type=int, default=16)
+    ap.add_argument("--little-maxit", type=int, default=16,
+                    help="little-solve iterations inside P_R for the exact solves")
+    ap.add_argument("--little-maxit-sloppy", type=int, default=4,
+                    help="little-solve iterations inside P_R for the sloppy solves")
     ap.add_argument("--chunk", type=int, default=4, help="source positions per ama_solve call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-rhs comparator")
@@ -317,7 +320,7 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sap_sloppy, dfl=d, little_tol=1e-6,
-                               little_maxit=args.little_maxit)
+                               little_maxit=args.little_maxit_sloppy)
         exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap_exact, dfl=d, little_tol=1e-10,
                               little_maxit=args.little_maxit)
         infs, infe = [], []
@@ -409,7 +412,8 @@ def main():
         "config": {"workload": args.workload, "lattice": "x".join(str(d) for d in dims), "block": list(block),
                    "Ns": 0 if args.no_deflation else args.ns, "positions": npos, "sloppy_rhs": 12 * npos,
                    "exact_rhs": 12, "sloppy_res": 3e-3, "exact_res": 1e-10,
-                   "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage], "ncy": 5, "nmr": 4},
+                   "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage], "ncy": 5, "nmr": 4,
+                   "little_maxit": {"sloppy": args.little_maxit_sloppy, "exact": args.little_maxit}},
         "roofline": roof,
         "stencil_roofline": stencil,
         "phases_s": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
@@ -423,7 +427,7 @@ def main():
         log("[bench] FP64 single-rhs comparator")
         ph = result["phases_s"]
         f64 = fp64_single_rhs(state["fld"], state["dfl"], pos, npos, ph["field"] + ph["deflation"],
-                              args.little_maxit, log)
+                              args.little_maxit, args.little_maxit_sloppy, log)
         f64["speedup_mixed"] = f64["value"] / s_per_source
         result["fp64_single_rhs"] = f64
     if not args.no_cpu_baseline:

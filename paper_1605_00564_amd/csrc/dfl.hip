@@ -569,15 +569,13 @@ int dfl_work(qcd_dfl d, size_t bytes, void **p) {
     if (bytes > d->lw_bytes) {
         if (d->lw) {
             DFL_HIP(hipDeviceSynchronize());
-            DFL_HIP(hipFree(d->lw));
+            ws_release(d->device, d->lw, d->lw_bytes);
         }
         d->lw = nullptr;
         d->lw_bytes = 0;
-        if (hipMalloc(&d->lw, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(QCD_ENOMEM, "deflation work space allocation failed");
-        }
-        d->lw_bytes = bytes;
+        size_t got = 0;
+        DFL_TRY(ws_acquire(d->device, bytes, &d->lw, &got));
+        d->lw_bytes = got;
     }
     *p = d->lw;
     return 0;
@@ -778,7 +776,8 @@ void dfl_free(qcd_dfl d) {
     (void)hipFree(d->boff);
     (void)hipFree(d->loc);
     (void)hipFree(d->blex);
-    (void)hipFree(d->lw);
+    (void)hipDeviceSynchronize();
+    ws_release(d->device, d->lw, d->lw_bytes);
     if (d->hp) (void)hipHostFree(d->hp);
     delete d;
 }
@@ -828,6 +827,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     if (prm->ninv < 0) return set_error(QCD_EINVAL, "ninv must be >= 0");
     qcd_dfl d = new qcd_dfl_s();
     d->f = f;
+    d->device = f->device;
     d->params = *prm;
     d->Ns = prm->Ns;
     d->Nb = g.Nb;

@@ -4,6 +4,7 @@
 
 struct qcd_dfl_s {
     qcd_field f = nullptr;
+    int device = 0;
     qcd_dfl_params params{};
     int Ns = 0, Nb = 0;
     // Phi: [Nb][Ns][6 chunks][2 parities][Vbh] float4, blocks in lexicographic

@@ -15,19 +15,84 @@ int set_error(int code, const std::string &msg) {
     return code;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace cache.  Scratch buffers are call-scoped (no call relies on what a
+// previous call left in them), so a buffer that a handle gives up (outgrown,
+// or the handle destroyed) is kept for the next handle on the same device
+// instead of being freed: a run over many gauge fields allocates its
+// workspace once (re-allocating some 200 GB per field costs about a second).
+// A cached buffer is handed out only for requests of at least half its size;
+// if an allocation fails, the device's cached buffers are freed and the
+// allocation retried.  Calls on handles that share a device must not overlap
+// in time on different streams (they share this workspace).
+// ---------------------------------------------------------------------------
+struct CachedBuf {
+    int dev;
+    void *p;
+    size_t bytes;
+};
+static std::mutex g_ws_mu;
+static std::vector<CachedBuf> g_ws_cache;
+
+int ws_acquire(int dev, size_t bytes, void **p, size_t *got) {
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        int best = -1;
+        for (size_t i = 0; i < g_ws_cache.size(); ++i) {
+            const CachedBuf &c = g_ws_cache[i];
+            if (c.dev == dev && c.bytes >= bytes && c.bytes / 2 <= bytes &&
+                (best < 0 || c.bytes < g_ws_cache[best].bytes))
+                best = (int)i;
+        }
+        if (best >= 0) {
+            *p = g_ws_cache[best].p;
+            *got = g_ws_cache[best].bytes;
+            g_ws_cache.erase(g_ws_cache.begin() + best);
+            return 0;
+        }
+    }
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        std::vector<void *> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_ws_mu);
+            for (size_t i = 0; i < g_ws_cache.size();)
+                if (g_ws_cache[i].dev == dev) {
+                    drop.push_back(g_ws_cache[i].p);
+                    g_ws_cache.erase(g_ws_cache.begin() + i);
+                } else {
+                    ++i;
+                }
+        }
+        if (drop.empty()) return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+        DFL_HIP(hipDeviceSynchronize());
+        for (void *q : drop) (void)hipFree(q);
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    *got = bytes;
+    return 0;
+}
+
+void ws_release(int dev, void *p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws_cache.push_back({dev, p, bytes});
+}
+
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p) {
     if (bytes > f->buf_bytes[slot]) {
         if (f->buf[slot]) {
             DFL_HIP(hipDeviceSynchronize());   // the old buffer may still be in use by queued work
-            DFL_HIP(hipFree(f->buf[slot]));
+            ws_release(f->device, f->buf[slot], f->buf_bytes[slot]);
         }
         f->buf[slot] = nullptr;
         f->buf_bytes[slot] = 0;
-        if (hipMalloc(&f->buf[slot], bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-        f->buf_bytes[slot] = bytes;
+        size_t got = 0;
+        DFL_TRY(ws_acquire(f->device, bytes, &f->buf[slot], &got));
+        f->buf_bytes[slot] = got;
     }
     *p = f->buf[slot];
     return 0;
@@ -445,6 +510,17 @@ const char *qcd_strerror(int code) {
 int qcd_prof_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    // create the events up front (two per launch, up to the fold bound), so
+    // that event creation does not land inside the measured launches
+    if (g_prof_on)
+        while (g_event_pool.size() < 2 * 4096 + 64) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            g_event_pool.push_back(e);
+        }
     return 0;
 }
 
@@ -616,7 +692,9 @@ int qcd_field_destroy(qcd_field f) {
     for (auto p : f->U) (void)hipFree(p);
     for (auto p : f->clo) (void)hipFree(p);
     for (auto p : f->cloinv) (void)hipFree(p);
-    for (auto p : f->buf) (void)hipFree(p);
+    // scratch goes back to the workspace cache once queued work is done
+    (void)hipDeviceSynchronize();
+    for (int k = 0; k < (int)(sizeof(f->buf) / sizeof(f->buf[0])); ++k) ws_release(f->device, f->buf[k], f->buf_bytes[k]);
     if (f->hp) (void)hipHostFree(f->hp);
     delete f;
     return 0;

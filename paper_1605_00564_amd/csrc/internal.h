@@ -59,8 +59,10 @@ int set_error(int code, const std::string &msg);
 // ---------------------------------------------------------------------------
 // complex arithmetic
 // ---------------------------------------------------------------------------
+// aligned to its size, so that one 8-byte (16-byte) LDS access with an
+// immediate offset moves a complex float (double)
 template <class R>
-struct cx {
+struct alignas(2 * sizeof(R)) cx {
     R re, im;
 };
 
@@ -606,6 +608,9 @@ enum BufSlot {
     BUF_RES = 8
 };
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
+// process-wide cache of call-scoped device workspace, per device
+int ws_acquire(int dev, size_t bytes, void **p, size_t *got);
+void ws_release(int dev, void *p, size_t bytes);
 
 // Profiling of kernel classes with HIP events.
 enum ProfClass { PROF_DIRAC = 0, PROF_SAP = 1, PROF_DFL = 2, PROF_LITTLE = 3, PROF_BLAS = 4, PROF_OTHER = 5 };

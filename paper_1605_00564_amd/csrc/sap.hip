@@ -89,12 +89,16 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
     for (int k = 0; k < 12; ++k) out[k] = rmac(out[k], -kappa, acc[k]);
 }
 
-template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT>
+// VBHC > 0: the block's sites per parity as a compile-time constant (the
+// component planes of the exchange buffers then sit at immediate LDS
+// offsets); 0: taken from the argument.
+template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0>
 __global__ void __launch_bounds__(MAXT)
     k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, const void *__restrict__ U,
                 const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr,
-                const short *__restrict__ lnbr, long V, long Vh, int Vbh, int nbc, int colour, R kappa, int nmr,
+                const short *__restrict__ lnbr, long V, long Vh, int Vbh_arg, int nbc, int colour, R kappa, int nmr,
                 int first, cx<R> *gbuf) {
+    const int Vbh = VBHC > 0 ? VBHC : Vbh_arg;
     extern __shared__ unsigned char dsm[];
     __shared__ R red[16][3];
     const int NT = blockDim.x;
@@ -334,9 +338,9 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
             const double by = pairs * (2.0 * Spin<S>::BYTES * (first ? 2 : 3)) + (double)nbc * Vbh * 2 *
                               (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
             ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
-#define DFL_SAP_LAUNCH(LDSV, KSV, MAXT)                                                                        \
+#define DFL_SAP_LAUNCH(LDSV, KSV, MAXT, VBHC)                                                                  \
     {                                                                                                          \
-        auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT>;                                                \
+        auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT, VBHC>;                                          \
         size_t sh = LDSV ? lds : 0;                                                                            \
         if (LDSV && sh > 64 * 1024) (void)hipFuncSetAttribute((const void *)kern,                              \
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
@@ -344,11 +348,13 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
                                   kappa, nmr, first, gbuf);                                                    \
     }
             if (use_lds) {
-                if (NT <= 256) DFL_SAP_LAUNCH(true, 1, 256)
-                else DFL_SAP_LAUNCH(true, 1, 1024)
+                if (Vbh == 128) DFL_SAP_LAUNCH(true, 1, 256, 128)
+                else if (Vbh == 256) DFL_SAP_LAUNCH(true, 1, 256, 256)
+                else if (NT <= 256) DFL_SAP_LAUNCH(true, 1, 256, 0)
+                else DFL_SAP_LAUNCH(true, 1, 1024, 0)
             } else {
-                if (KS == 1) DFL_SAP_LAUNCH(false, 1, 1024)
-                else DFL_SAP_LAUNCH(false, 2, 1024)
+                if (KS == 1) DFL_SAP_LAUNCH(false, 1, 1024, 0)
+                else DFL_SAP_LAUNCH(false, 2, 1024, 0)
             }
 #undef DFL_SAP_LAUNCH
         }
