@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--ninv", type=int, default=5)
     ap.add_argument("--no-deflation", action="store_true")
     ap.add_argument("--sloppy-storage", type=int, default=F16)
-    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=24, help="right-hand sides per solver launch (0: from free memory)")
     ap.add_argument("--little-maxit", type=int, default=16,
                     help="little-solve iterations inside P_R for the exact solves")
     ap.add_argument("--little-maxit-sloppy", type=int, default=4,

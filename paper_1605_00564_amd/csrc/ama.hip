@@ -46,6 +46,7 @@ int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
         (void)hipGetLastError();
         return 12;
     }
+    freeb += ws_cached_bytes(f->device);   // cached workspace is reusable
     const size_t V = f->g.V;
     const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
     const size_t per = V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5);

@@ -76,6 +76,14 @@ int ws_acquire(int dev, size_t bytes, void **p, size_t *got) {
     return 0;
 }
 
+size_t ws_cached_bytes(int dev) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    size_t n = 0;
+    for (const CachedBuf &c : g_ws_cache)
+        if (c.dev == dev) n += c.bytes;
+    return n;
+}
+
 void ws_release(int dev, void *p, size_t bytes) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(g_ws_mu);

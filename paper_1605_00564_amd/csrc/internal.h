@@ -611,6 +611,7 @@ int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
 // process-wide cache of call-scoped device workspace, per device
 int ws_acquire(int dev, size_t bytes, void **p, size_t *got);
 void ws_release(int dev, void *p, size_t bytes);
+size_t ws_cached_bytes(int dev);   // held in the cache, available to new requests
 
 // Profiling of kernel classes with HIP events.
 enum ProfClass { PROF_DIRAC = 0, PROF_SAP = 1, PROF_DFL = 2, PROF_LITTLE = 3, PROF_BLAS = 4, PROF_OTHER = 5 };
