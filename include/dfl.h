@@ -221,6 +221,25 @@ int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const 
               qcd_info *info_sloppy /* host [npos*12] */, qcd_info *info_exact /* host [nexact*12] */,
               hipStream_t stream);
 
+/* Sources built on the device, canonical [n][V][4][3] at io precision.
+ *
+ * Z2 noise (stochastic sources for all-mode averaging, section 2.1): real
+ * +-1 on every component; component j = 12 lex + spin-colour of noise
+ * vector k = index0 + r takes the sign of the top bit of SplitMix64 output
+ * 12 V k + j, SplitMix64 started at the state sm64(seed, 6) (output 6 of
+ * the sequence started at `seed`).  out: caller-owned device buffer of n
+ * vectors. */
+int make_z2_sources(qcd_field f, unsigned long long seed, long long index0, int n, void *out, qcd_prec io,
+                    hipStream_t stream);
+
+/* Sequential sources (three-point functions, section 2.3): eta_r(x) =
+ * delta_{t(x), t_sink} gamma_5 gamma_mu gamma_5 psi_r(x) for n forward
+ * solutions psi (device, canonical), in the chiral basis of the operator.
+ * psi and eta must not overlap.  Errors: mu outside 0..3 or t_sink outside
+ * the lattice give QCD_EINVAL. */
+int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_prec io, int t_sink, int mu,
+                            hipStream_t stream);
+
 /* Kernel timing with HIP events on the launch stream, for measurement.
  * Classes: 0 Dirac stencil, 1 SAP block sweep, 2 deflation projection and
  * prolongation, 3 little operator, 4 vector algebra, 5 other. */

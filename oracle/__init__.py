@@ -471,6 +471,20 @@ def solve(op: Operator, b, block=None, ncy=5, nmr=4, dfl: Deflation = None, nkv=
     return gcr(op.M, prec, b, x0=x0, nkv=nkv, nmx=nmx, res=res, fixed_iters=fixed_iters)
 
 
+def sequential_source(psi, dims, t_sink, mu=3):
+    """Sequential source for a three-point function (section 2.3): the
+    forward solution with the insertion gamma_5 gamma_mu gamma_5 on the sink
+    timeslice, zero elsewhere.  psi: [..., V, 4, 3]."""
+    g, _ = gamma_matrices()
+    G = g[4] @ g[mu] @ g[4]
+    V = synth.volume(dims)
+    spatial = V // dims[0]
+    sel = (np.arange(V) // spatial) == t_sink
+    out = np.zeros_like(psi, dtype=np.complex128)
+    out[..., sel, :, :] = np.einsum("st,...vtc->...vsc", G, psi[..., sel, :, :])
+    return out
+
+
 def ama_positions(dims, block, x0, steps):
     """Source positions x0 + g for a regular grid of shifts g (all-mode
     averaging, section 2.1) that map the block checkerboard onto itself

@@ -83,6 +83,8 @@ def load():
     L.qcd_field_destroy.argtypes = [P]
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
     L.dirac_apply_ex.argtypes = [P, P, P, I, I, I, I, I, P]
+    L.make_z2_sources.argtypes = [P, C.c_ulonglong, C.c_longlong, I, P, I, P]
+    L.make_sequential_sources.argtypes = [P, P, P, I, I, I, I, P]
     L.sap_precond.argtypes = [P, C.POINTER(_Sap), P, P, I, I, P]
     for name, args in [
         ("deflation_setup", [P, C.POINTER(_DflParams), P, C.POINTER(P)]),
@@ -319,6 +321,26 @@ def dirac_apply(field: Field, x, storage: int = F64, out=None, spinor_in=None, s
     so = dflt if spinor_out is None else spinor_out
     _check(load().dirac_apply_ex(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _io_of(x),
                                  storage, si, so, _stream()), "dirac_apply_ex")
+    return out
+
+
+def z2_sources(field: Field, seed: int, n: int, index0: int = 0, dtype=None):
+    """n Z2-noise source vectors [n, V, 4, 3] built on the device."""
+    torch = _torch()
+    dtype = dtype or torch.complex64
+    out = torch.empty((n, field.V, 4, 3), dtype=dtype, device="cuda")
+    _check(load().make_z2_sources(field.handle, seed, index0, n, C.c_void_p(out.data_ptr()), _io_of(out), _stream()),
+           "make_z2_sources")
+    return out
+
+
+def sequential_sources(field: Field, psi, t_sink: int, mu: int = 3, out=None):
+    """eta = delta_{t, t_sink} gamma_5 gamma_mu gamma_5 psi for each vector of psi."""
+    torch = _torch()
+    n = _vec(psi, field.V)
+    out = torch.empty_like(psi) if out is None else out
+    _check(load().make_sequential_sources(field.handle, C.c_void_p(psi.data_ptr()), C.c_void_p(out.data_ptr()), n,
+                                          _io_of(psi), t_sink, mu, _stream()), "make_sequential_sources")
     return out
 
 

@@ -17,18 +17,6 @@ qcd_field dfl_field(qcd_dfl d) { return d->f; }
 // complex number j = (l V + i) 12 + sc; its real and imaginary parts are the
 // cosine and sine branches of Box-Muller on outputs 2j and 2j+1.
 // ---------------------------------------------------------------------------
-__device__ inline unsigned long long sm64(unsigned long long key, unsigned long long n) {
-    unsigned long long z = key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-static unsigned long long sm64_host(unsigned long long key, unsigned long long n) {
-    unsigned long long z = key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
 
 __global__ void k_random_fields(float4 *__restrict__ v, unsigned long long key, const int *__restrict__ lex_of,
                                 long V) {
@@ -898,7 +886,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     int rc = field_buffer(f, BUF_AMA, sizeof(float4) * 6 * V * (size_t)Ns * 2, &vp);
     if (rc < 0) return fail(rc);
     float4 *v = static_cast<float4 *>(vp), *w = v + (size_t)6 * V * Ns;
-    const unsigned long long key = sm64_host(prm->seed, 5ULL);   // stream 5: deflation fields
+    const unsigned long long key = sm64(prm->seed, 5ULL);   // stream 5: deflation fields
     k_random_fields<<<dim3(nblocks(V, 256), Ns), 256, 0, s>>>(v, key, f->lex_of, V);
     if ((e = hipGetLastError()) != hipSuccess) return fail(set_error(QCD_EHIP, hipGetErrorString(e)));
     void *sp;

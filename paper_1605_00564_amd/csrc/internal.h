@@ -533,6 +533,15 @@ __device__ inline void hop(const cx<R> w[9], const cx<R> psi[12], R sign, cx<R> 
     reconstruct_add<R, MU, S>(g, sign, acc);
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: output
+// n of the sequence started at state `key`
+__host__ __device__ inline unsigned long long sm64(unsigned long long key, unsigned long long n) {
+    unsigned long long z = key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
 // A pointer the caller knows to be the same in every lane, marked as such:
 // buffer loads need their descriptor in scalar registers, and where the
 // compiler cannot prove a base uniform it wraps each load in a loop over

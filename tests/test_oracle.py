@@ -60,6 +60,21 @@ def test_gamma_algebra_matches_typed_basis():
         assert np.abs(sig[p][:2, 2:]).max() == 0 and np.abs(sig[p][2:, :2]).max() == 0
 
 
+def test_sequential_source_is_minus_gamma_mu_on_the_sink_timeslice():
+    """gamma_5 anticommutes with gamma_mu, so the insertion equals -gamma_mu
+    (typed basis) on the sink timeslice and the source vanishes elsewhere."""
+    dims = (4, 2, 2, 2)
+    gt, _ = _gammas_typed()
+    psi = synth.gaussian_spinor(dims, 2, 1007)
+    for mu in range(4):
+        eta = oracle.sequential_source(psi, dims, 2, mu)
+        V = synth.volume(dims)
+        t = np.arange(V) // (V // dims[0])
+        assert np.abs(eta[:, t != 2]).max() == 0
+        ref = -np.einsum("st,rvtc->rvsc", gt[mu], psi[:, t == 2])
+        assert np.allclose(eta[:, t == 2], ref, atol=1e-15)
+
+
 # ---------------------------------------------------------------------------
 # Free field: plane waves are eigenvectors with the closed-form symbol
 # ---------------------------------------------------------------------------
