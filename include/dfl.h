@@ -221,6 +221,22 @@ int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const 
               qcd_info *info_sloppy /* host [npos*12] */, qcd_info *info_exact /* host [nexact*12] */,
               hipStream_t stream);
 
+/* The solve of gcr_solve for nrhs right-hand sides given one by one
+ * (b[r], x[r]: caller-owned device pointers to canonical [V][4][3] vectors
+ * at io precision), in batches of `batch` (0: 12).  With graph != 0 the
+ * solve must have a fixed iteration count (p->fixed_iters > 0, the
+ * truncated solves of section 3.5, Table 3): it then runs without host
+ * synchronisation, and its launches for one batch size are captured once
+ * into a HIP graph (on a stream the handle owns) and replayed for every
+ * later batch of that size, on `stream`.  Little solves inside then run
+ * their fixed budget (p->little_maxit).  info[r].rel_res is the FP64
+ * relative residual after the fixed iterations; status QCD_NOCONV if it is
+ * above p->res.  Graphs are kept in the handle until a workspace buffer
+ * grows or the handle is destroyed.  Calls must not overlap in time with
+ * other calls on the same handle. */
+int gcr_solve_batched(qcd_field f, const qcd_gcr *p, const void *const *b, void *const *x, int nrhs, qcd_prec io,
+                      int batch, int graph, qcd_info *info /* host [nrhs] */, hipStream_t stream);
+
 /* Sources built on the device, canonical [n][V][4][3] at io precision.
  *
  * Z2 noise (stochastic sources for all-mode averaging, section 2.1): real

@@ -84,6 +84,7 @@ def load():
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
     L.dirac_apply_ex.argtypes = [P, P, P, I, I, I, I, I, P]
     L.make_z2_sources.argtypes = [P, C.c_ulonglong, C.c_longlong, I, P, I, P]
+    L.gcr_solve_batched.argtypes = [P, C.POINTER(_Gcr), C.POINTER(P), C.POINTER(P), I, I, I, I, C.POINTER(_Info), P]
     L.make_sequential_sources.argtypes = [P, P, P, I, I, I, I, P]
     L.sap_precond.argtypes = [P, C.POINTER(_Sap), P, P, I, I, P]
     for name, args in [
@@ -366,6 +367,26 @@ def gcr_solve(field: Field, b, params: GcrParams = None, x=None):
                           _io_of(b), info, _stream())
     _check(rc, "gcr_solve", ok_noconv=True)
     return x, [SolveInfo(i.status, i.iters, i.rel_res) for i in info]
+
+
+def gcr_solve_batched(field: Field, b_list, params: GcrParams, x_list=None, batch: int = 0, graph: bool = False):
+    """Solve every vector of b_list (each [V, 4, 3] on the GPU, contiguous)
+    in batches; with graph=True (needs params.fixed_iters > 0) the batches
+    replay one captured HIP graph per batch size.  Returns (x_list, info)."""
+    torch = _torch()
+    n = len(b_list)
+    x_list = x_list if x_list is not None else [torch.empty_like(v) for v in b_list]
+    for v in list(b_list) + list(x_list):
+        if not v.is_contiguous() or v.numel() != field.V * 12:
+            raise ValueError("vectors must be contiguous [V, 4, 3]")
+    bp = (C.c_void_p * n)(*[v.data_ptr() for v in b_list])
+    xp = (C.c_void_p * n)(*[v.data_ptr() for v in x_list])
+    p = params.c()
+    info = (_Info * n)()
+    rc = load().gcr_solve_batched(field.handle, C.byref(p), bp, xp, n, _io_of(b_list[0]), batch, 1 if graph else 0,
+                                  info, _stream())
+    _check(rc, "gcr_solve_batched", ok_noconv=True)
+    return x_list, [SolveInfo(i.status, i.iters, i.rel_res) for i in info]
 
 
 def ama_solve(field: Field, positions, exact_flags, sloppy: GcrParams, exact: GcrParams, dtype=None, batch=0,

@@ -37,6 +37,7 @@ int gcr_trisolve(const double *R, const double *cvec, int n, int k, double *alph
 // per-solve scalar work space: partial sums, reductions, R, c, alpha
 struct Scal {
     double *part, *red, *red2, *R, *cvec, *coef, *alpha;
+    double *bn2;   // ||b||^2 per rhs, kept on the device by solves that do not synchronise
 };
 size_t scalar_bytes(int n);
 int scalar_buffers_at(void *p, int n, Scal &sc);

@@ -432,6 +432,8 @@ int scalar_buffers_at(void *p, int n, Scal &sc) {
     sc.coef = d;
     d += 3 * (size_t)n;
     sc.alpha = d;
+    d += nc;
+    sc.bn2 = d;
     return 0;
 }
 
@@ -441,7 +443,7 @@ size_t scalar_bytes(int n) {
     const size_t nred = (size_t)n * 2 * NKV_MAX;
     const size_t nR = (size_t)n * NKV_MAX * NKV_MAX * 2;
     const size_t nc = (size_t)n * NKV_MAX * 2;
-    return (npart + 2 * nred + nR + nc + 3 * (size_t)n + nc) * sizeof(double);
+    return (npart + 2 * nred + nR + nc + 3 * (size_t)n + nc + (size_t)n) * sizeof(double);
 }
 
 #define DFL_INST(E)                                                                                      \

@@ -555,6 +555,8 @@ namespace {
 
 int dfl_work(qcd_dfl d, size_t bytes, void **p) {
     if (bytes > d->lw_bytes) {
+        if (capturing()) return set_error(QCD_EINVAL, "workspace growth during stream capture");
+        ++d->f->graph_gen;
         if (d->lw) {
             DFL_HIP(hipDeviceSynchronize());
             ws_release(d->device, d->lw, d->lw_bytes);
@@ -778,7 +780,8 @@ int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int
     DFL_TRY(field_buffer(d->f, BUF_DFL, 2 * nv * sizeof(double2), &p));
     double2 *u = static_cast<double2 *>(p), *c = u + nv;
     DFL_TRY(restrict_v<double2>(d, b, u, n, s));
-    int rc = little_solve(d, u, c, n, tol, maxit, true, nullptr, nullptr, s);
+    // polled to tol, except without host synchronisation (fixed budget)
+    int rc = little_solve(d, u, c, n, tol, maxit, !nosync(), nullptr, nullptr, s);
     if (rc < 0) return rc;
     return prolong_v<double2, 2>(d, x, c, n, s);
 }

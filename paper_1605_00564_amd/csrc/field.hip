@@ -90,8 +90,16 @@ void ws_release(int dev, void *p, size_t bytes) {
     g_ws_cache.push_back({dev, p, bytes});
 }
 
+static thread_local bool g_nosync = false, g_capturing = false;
+void set_nosync(bool on) { g_nosync = on; }
+bool nosync() { return g_nosync; }
+void set_capturing(bool on) { g_capturing = on; }
+bool capturing() { return g_capturing; }
+
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p) {
     if (bytes > f->buf_bytes[slot]) {
+        if (g_capturing) return set_error(QCD_EINVAL, "workspace growth during stream capture");
+        ++f->graph_gen;
         if (f->buf[slot]) {
             DFL_HIP(hipDeviceSynchronize());   // the old buffer may still be in use by queued work
             ws_release(f->device, f->buf[slot], f->buf_bytes[slot]);
@@ -133,6 +141,7 @@ static hipEvent_t take_event() {
 }
 
 ProfScope::ProfScope(int c, hipStream_t st, double flops, double bytes, double units) : cls(c), s(st) {
+    if (g_nosync) return;   // captured work is timed as a whole by the caller
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     g_prof_work[c][0] += flops;
@@ -702,6 +711,8 @@ int qcd_field_destroy(qcd_field f) {
     for (auto p : f->cloinv) (void)hipFree(p);
     // scratch goes back to the workspace cache once queued work is done
     (void)hipDeviceSynchronize();
+    graph_cache_free(f);
+    if (f->cap) (void)hipStreamDestroy(f->cap);
     for (int k = 0; k < (int)(sizeof(f->buf) / sizeof(f->buf[0])); ++k) ws_release(f->device, f->buf[k], f->buf_bytes[k]);
     if (f->hp) (void)hipHostFree(f->hp);
     delete f;

@@ -78,9 +78,14 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     DFL_TRY(field_buffer(f, BUF_RED, scalar_bytes(n), &sp));
     DFL_TRY(scalar_buffers_at(sp, n, sc));
 
-    std::vector<double> h;
-    DFL_TRY(blas_norm2(b, ne64, n, sc.part, sc.red, s));
-    DFL_TRY(fetch(f, sc.red, n, s, h));
+    // Without host synchronisation (stream capture) the norms stay on the
+    // device: ||b||^2 in sc.bn2, the final ||r||^2 in sc.red, read by the
+    // caller after the captured work ran; iteration counts are fixed.
+    const bool ns = nosync();
+    if (ns && p->fixed_iters <= 0) return set_error(QCD_EINVAL, "solves without synchronisation need fixed_iters");
+    std::vector<double> h(n, 1.0);
+    DFL_TRY(blas_norm2(b, ne64, n, sc.part, ns ? sc.bn2 : sc.red, s));
+    if (!ns) DFL_TRY(fetch(f, sc.red, n, s, h));
     std::vector<double> bn(n);
     for (int i = 0; i < n; ++i) {
         if (!std::isfinite(h[i])) return set_error(QCD_ENAN, "NaN or Inf in the right-hand side");
@@ -98,8 +103,9 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     // part of r outside it, left by inexact little solves and FP32 rounding,
     // is removed here, in FP64, before the next cycle.
     auto low_mode_correction = [&]() -> int {
-        DFL_TRY(dfl_low_mode(p->dfl, r, x, n, p->little_tol, std::max(p->little_maxit, 200), s));
+        DFL_TRY(dfl_low_mode(p->dfl, r, x, n, p->little_tol, ns ? p->little_maxit : std::max(p->little_maxit, 200), s));
         DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
+        if (ns) return 0;
         DFL_TRY(fetch(f, sc.red, n, s, h));
         for (int i = 0; i < n; ++i) rn[i] = std::sqrt(h[i]);
         return 0;
@@ -155,13 +161,16 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         DFL_TRY(gcr_trisolve(sc.R, sc.cvec, n, k, sc.alpha, s));
         DFL_TRY(accum(x, Z, V, n, k, sc.alpha, s));
         DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
-        DFL_TRY(fetch(f, sc.red, n, s, h));
-        for (int i = 0; i < n; ++i) {
-            if (!std::isfinite(h[i])) return set_error(QCD_ENAN, "NaN in the recomputed residual");
-            rn[i] = std::sqrt(h[i]);
+        if (!ns) {
+            DFL_TRY(fetch(f, sc.red, n, s, h));
+            for (int i = 0; i < n; ++i) {
+                if (!std::isfinite(h[i])) return set_error(QCD_ENAN, "NaN in the recomputed residual");
+                rn[i] = std::sqrt(h[i]);
+            }
         }
         if (p->fixed_iters > 0 ? iters >= p->fixed_iters : converged(rn)) done = true;
     }
+    if (ns) return 0;
     bool all = true;
     for (int i = 0; i < n; ++i) {
         const double rel = bn[i] > 0 ? rn[i] / bn[i] : 0.0;

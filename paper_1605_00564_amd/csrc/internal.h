@@ -606,6 +606,9 @@ struct qcd_field_s {
     void *buf[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     size_t buf_bytes[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
+    unsigned graph_gen = 0;  // bumped whenever a scratch buffer moves (captured graphs refer to them)
+    void *graphs = nullptr;  // captured solve graphs (owned; see batched.hip)
+    hipStream_t cap = nullptr;  // library stream used for stream capture
     double *hp = nullptr;    // pinned host scratch (4096 doubles)
 };
 
@@ -617,6 +620,17 @@ enum BufSlot {
     BUF_RES = 8
 };
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
+// Solver mode without host synchronisation (for stream capture into a HIP
+// graph): no host reads of norms, fixed iteration counts, little solves with
+// a fixed budget, no profiling events.  Per host thread.
+void set_nosync(bool on);
+bool nosync();
+// set while a solve is being captured: workspace must not grow (a captured
+// graph keeps the addresses it saw)
+void set_capturing(bool on);
+bool capturing();
+// captured graphs of a field handle (batched solves); freed with the handle
+void graph_cache_free(qcd_field f);
 // process-wide cache of call-scoped device workspace, per device
 int ws_acquire(int dev, size_t bytes, void **p, size_t *got);
 void ws_release(int dev, void *p, size_t bytes);

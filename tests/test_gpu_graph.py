@@ -1,0 +1,94 @@
+"""Batched fixed-iteration solves replayed from captured HIP graphs.
+
+A replay must reproduce, bit for bit, what the same launches compute when
+run eagerly: the first batch of each size is run eagerly (without host
+synchronisation) and captured, later batches of that size replay the graph.
+A fresh handle solving a replayed batch first (eagerly) is the reference.
+The replays are repeated with eager torch work and synchronisations in
+between, over an uneven mix of Z2-noise and point sources (batches of 4, 4
+and 2), and the residuals they report are checked with the oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F16 = 2
+DIMS, BLOCK = (8, 8, 8, 8), (4, 4, 4, 4)
+
+
+def _gpu():
+    import torch
+    import paper_1605_00564_amd as dfl
+    return torch, dfl
+
+
+def make(U, torch, dfl):
+    fld = dfl.Field(DIMS, BLOCK, 0.124, 1.5, U)
+    sap = dfl.SapParams(5, 4, F16)
+    d = dfl.Deflation(fld, Ns=8, ninv=3, seed=7, sap=sap)
+    p = dfl.GcrParams(nkv=4, fixed_iters=2, res=3e-3, sap=sap, dfl=d, little_tol=1e-6, little_maxit=6)
+    return fld, d, p
+
+
+def sources(torch, dfl, fld):
+    z = dfl.z2_sources(fld, seed=2, n=5, dtype=torch.complex128)
+    V = synth.volume(DIMS)
+    pts = []
+    for k in range(5):
+        e = np.zeros((V, 4, 3), np.complex128)
+        e[(37 * k + 11) % V, k % 4, k % 3] = 1.0
+        pts.append(torch.from_numpy(e).cuda())
+    # uneven mix: Z2 and point sources interleaved
+    return [z[0], pts[0], z[1], pts[1], z[2], pts[2], z[3], pts[3], z[4], pts[4]]
+
+
+def test_graph_replay_matches_eager_solves():
+    torch, dfl = _gpu()
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    op = oracle.Operator(DIMS, U, 0.124, 1.5, -1)
+    fld, d, p = make(U, torch, dfl)
+    b = sources(torch, dfl, fld)
+    runs = []
+    for rep in range(3):
+        x, info = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)
+        runs.append(([v.cpu().numpy() for v in x], info))
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        _ = float(junk.square().sum())
+        torch.cuda.synchronize()
+    for rep in (1, 2):
+        for r in range(10):
+            assert np.array_equal(runs[rep][0][r], runs[0][0][r]), (rep, r)
+    # reference: a fresh handle computes batch 1 (sources 4..7) eagerly first
+    fld2, d2, p2 = make(U, torch, dfl)
+    b2 = [b[k].clone() for k in (4, 5, 6, 7)]
+    x2, info2 = dfl.gcr_solve_batched(fld2, b2, p2, batch=4, graph=True)
+    for k, r in enumerate((4, 5, 6, 7)):
+        assert np.array_equal(x2[k].cpu().numpy(), runs[0][0][r]), r
+        assert info2[k].rel_res == runs[0][1][r].rel_res
+    # reported residuals are the FP64 residuals of the returned solutions
+    for r in (0, 1, 8, 9):
+        bb = b[r].cpu().numpy()
+        rr = oracle.norm(bb - op.M(runs[0][0][r])) / oracle.norm(bb)
+        assert abs(rr - runs[0][1][r].rel_res) <= 1e-9 * rr, (r, rr, runs[0][1][r].rel_res)
+        assert runs[0][1][r].iters == 2
+    for h in (d2, fld2, d, fld):
+        h.close()
+
+
+def test_graph_mode_requires_fixed_iterations():
+    torch, dfl = _gpu()
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    fld, d, p = make(U, torch, dfl)
+    p.fixed_iters = 0
+    b = sources(torch, dfl, fld)[:2]
+    with pytest.raises(dfl.DflError) as e:
+        dfl.gcr_solve_batched(fld, b, p, batch=2, graph=True)
+    assert e.value.code == -1
+    d.close()
+    fld.close()
