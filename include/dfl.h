@@ -256,6 +256,37 @@ int make_z2_sources(qcd_field f, unsigned long long seed, long long index0, int 
 int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_prec io, int t_sink, int mu,
                             hipStream_t stream);
 
+/* Launch choices of a handle's Dirac stencil, for the autotuner:
+ * QCD_TUNE_STENCIL_BLOCK  1 = one workgroup per Schwarz block with the
+ *                         block's spinors staged in LDS (when it fits),
+ *                         0 = site tiles;
+ * QCD_TUNE_STENCIL_RG     right-hand sides per site tile: 0 (automatic),
+ *                         1, 2 or 4;
+ * QCD_TUNE_STENCIL_ORDER  1 = site tiles in lexicographic block order,
+ *                         0 = memory order.
+ * Results do not depend on these; graphs captured on the handle are
+ * dropped.  Unknown knob or value: QCD_EINVAL. */
+#define QCD_TUNE_STENCIL_BLOCK 0
+#define QCD_TUNE_STENCIL_RG 1
+#define QCD_TUNE_STENCIL_ORDER 2
+int qcd_field_tune(qcd_field f, int knob, int value);
+
+/* Process-wide workspace cache.  Scratch buffers that a handle gives up
+ * (outgrown, or the handle destroyed) are kept for later handles on the
+ * same device; a cached buffer serves requests of half its size up to its
+ * size.  qcd_workspace_cached stores in *bytes what the cache holds for a
+ * device (memory that the device's free-memory query counts as used);
+ * qcd_workspace_trim frees it (device < 0: every device), waiting for the
+ * device first.  Buffers held by live handles are not touched.  Neither
+ * call may overlap a call that uses the workspace.  Null bytes: QCD_EINVAL. */
+int qcd_workspace_cached(int device, size_t *bytes);
+int qcd_workspace_trim(int device);
+/* Hand a handle's scratch buffers back to the workspace cache (after its
+ * queued work is done), so that another handle of the same lattice reuses
+ * them; the handle allocates again on its next call, and its captured
+ * graphs are dropped.  Null handle: QCD_EINVAL. */
+int qcd_field_trim(qcd_field f);
+
 /* Kernel timing with HIP events on the launch stream, for measurement.
  * Classes: 0 Dirac stencil, 1 SAP block sweep, 2 deflation projection and
  * prolongation, 3 little operator, 4 vector algebra, 5 other. */

@@ -12,5 +12,5 @@ from ._lib import (  # noqa: F401
     F64, F32, F16, BF16, NOCONV,
     DflError, Field, Deflation, SapParams, GcrParams, SolveInfo,
     lib_path, load, dirac_apply, sap_precond, gcr_solve, gcr_solve_batched, ama_solve, z2_sources, sequential_sources,
-    prof_enable, prof_reset, prof_get, PROF_CLASSES,
+    workspace_cached, workspace_trim, prof_enable, prof_reset, prof_get, PROF_CLASSES,
 )

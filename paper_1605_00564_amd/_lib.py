@@ -84,6 +84,7 @@ def load():
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
     L.dirac_apply_ex.argtypes = [P, P, P, I, I, I, I, I, P]
     L.make_z2_sources.argtypes = [P, C.c_ulonglong, C.c_longlong, I, P, I, P]
+    L.qcd_field_tune.argtypes = [P, I, I]
     L.gcr_solve_batched.argtypes = [P, C.POINTER(_Gcr), C.POINTER(P), C.POINTER(P), I, I, I, I, C.POINTER(_Info), P]
     L.make_sequential_sources.argtypes = [P, P, P, I, I, I, I, P]
     L.sap_precond.argtypes = [P, C.POINTER(_Sap), P, P, I, I, P]
@@ -99,6 +100,9 @@ def load():
         ("deflation_prolong", [P, P, P, I, I, P]),
         ("gcr_solve", [P, C.POINTER(_Gcr), P, P, I, I, C.POINTER(_Info), P]),
         ("ama_solve", [P, C.POINTER(_Ama), C.POINTER(P), C.POINTER(P), I, C.POINTER(_Info), C.POINTER(_Info), P]),
+        ("qcd_workspace_cached", [I, C.POINTER(C.c_size_t)]),
+        ("qcd_workspace_trim", [I]),
+        ("qcd_field_trim", [P]),
         ("qcd_prof_enable", [I]),
         ("qcd_prof_reset", []),
         ("qcd_prof_get", [I, C.POINTER(D), C.POINTER(C.c_longlong)]),
@@ -213,6 +217,16 @@ class Field:
                    "qcd_field_create")
         self.handle = h
         self.kappa, self.csw, self.bc_t = float(kappa), float(csw), int(bc_t)
+
+    TUNE_STENCIL_BLOCK, TUNE_STENCIL_RG, TUNE_STENCIL_ORDER = 0, 1, 2
+
+    def tune(self, knob: int, value: int):
+        """Set a launch choice of the Dirac stencil (see include/dfl.h)."""
+        _check(load().qcd_field_tune(self.handle, knob, value), "qcd_field_tune")
+
+    def trim(self):
+        """Give this handle's scratch buffers to the workspace cache."""
+        _check(load().qcd_field_trim(self.handle), "qcd_field_trim")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -417,6 +431,19 @@ def ama_solve(field: Field, positions, exact_flags, sloppy: GcrParams, exact: Gc
     _check(rc, "ama_solve", ok_noconv=True)
     conv = lambda arr, n: [SolveInfo(i.status, i.iters, i.rel_res) for i in arr[:n]]
     return xs, xe, conv(info_s, 12 * npos), conv(info_e, 12 * nex)
+
+
+def workspace_cached(device: int = 0) -> int:
+    """Bytes the process-wide workspace cache holds on a device (free for
+    later handles, but counted as used by the device's free-memory query)."""
+    n = C.c_size_t()
+    _check(load().qcd_workspace_cached(device, C.byref(n)), "workspace_cached")
+    return n.value
+
+
+def workspace_trim(device: int = -1):
+    """Free the cached workspace of a device (-1: every device)."""
+    _check(load().qcd_workspace_trim(device), "workspace_trim")
 
 
 def prof_enable(on: bool = True):

@@ -859,8 +859,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
         }
     }
 #define DALLOC(ptr, bytes)                                                                 \
-    if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                              \
-        (void)hipGetLastError();                                                          \
+    if (!dev_alloc(d->device, (void **)&(ptr), (bytes))) {                                \
         return fail(set_error(QCD_ENOMEM, "device allocation failed in deflation_setup")); \
     }
     DALLOC(d->phi, sizeof(float4) * (size_t)Nb * Ns * 12 * g.Vbh);

@@ -232,29 +232,17 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
     const double sbytes = (double)Spin<S>::BYTES + Spin<SO>::BYTES;
     auto work = [&](int n) { return std::make_tuple(1872.0 * V * n, V * (4 * lbytes + cbytes + n * sbytes), 1.0 * V * n); };
-    // right-hand sides per site group (tuning knob; 0 = automatic)
-    static const int rg_env = [] {
-        const char *e = getenv("DFL_STENCIL_RG");
-        return e ? atoi(e) : 0;
-    }();
-    int rg = rg_env > 0 ? rg_env : (nrhs >= 2 ? 2 : 1);
-    // tile order (tuning knob): 1 = lexicographic blocks, 0 = memory order
-    static const int ord_env = [] {
-        const char *e = getenv("DFL_STENCIL_ORDER");
-        return e ? atoi(e) : 1;
-    }();
-    const int *border = ord_env ? f->border : nullptr;
+    // tuning knobs of the handle: right-hand sides per site tile (0 =
+    // automatic), tile order (lexicographic blocks or memory order), and
+    // the block-staged kernel when the block fits one workgroup and its
+    // spinors fit 64 KB of LDS
+    const int rg = f->st_rg > 0 ? f->st_rg : (nrhs >= 2 ? 2 : 1);
+    const int *border = f->st_order ? f->border : nullptr;
     auto [fl, by, un] = work(nrhs);
     ProfScope ps(PROF_DIRAC, s, fl, by, un);
-    // kernel choice (tuning knob): block-staged when the block fits one
-    // workgroup and its spinors fit 64 KB of LDS, else site tiles
-    static const int blk_env = [] {
-        const char *e = getenv("DFL_STENCIL_BLOCK");
-        return e ? atoi(e) : 1;
-    }();
     const int Vb = 2 * f->g.Vbh;
     const size_t lds = (size_t)Spin<S>::BYTES * Vb;
-    if (blk_env && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(R) == 4)) {
+    if (f->st_block && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(R) == 4)) {
         const dim3 grid((unsigned)f->g.Nb, (unsigned)nrhs);
 #define DFL_BLK_LAUNCH(MAXT)                                                                                  \
     k_dirac_blk<S, SO, R, LF, CF, MAXT><<<grid, Vb, lds, s>>>(in, out, U, C, f->nbr, f->lnbr, f->border, V,      \

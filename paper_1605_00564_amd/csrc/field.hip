@@ -51,29 +51,38 @@ int ws_acquire(int dev, size_t bytes, void **p, size_t *got) {
             return 0;
         }
     }
-    if (hipMalloc(p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        std::vector<void *> drop;
-        {
-            std::lock_guard<std::mutex> lk(g_ws_mu);
-            for (size_t i = 0; i < g_ws_cache.size();)
-                if (g_ws_cache[i].dev == dev) {
-                    drop.push_back(g_ws_cache[i].p);
-                    g_ws_cache.erase(g_ws_cache.begin() + i);
-                } else {
-                    ++i;
-                }
-        }
-        if (drop.empty()) return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
-        DFL_HIP(hipDeviceSynchronize());
-        for (void *q : drop) (void)hipFree(q);
-        if (hipMalloc(p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-    }
+    if (!dev_alloc(dev, p, bytes))
+        return set_error(QCD_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
     *got = bytes;
     return 0;
+}
+
+// hipMalloc on the current device (dev); when it fails, the device's cached
+// workspace is freed and the allocation tried once more
+bool dev_alloc(int dev, void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    std::vector<void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (size_t i = 0; i < g_ws_cache.size();)
+            if (g_ws_cache[i].dev == dev) {
+                drop.push_back(g_ws_cache[i].p);
+                g_ws_cache.erase(g_ws_cache.begin() + i);
+            } else {
+                ++i;
+            }
+    }
+    if (drop.empty()) return false;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    for (void *q : drop) (void)hipFree(q);
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
 }
 
 size_t ws_cached_bytes(int dev) {
@@ -524,6 +533,66 @@ const char *qcd_strerror(int code) {
     }
 }
 
+int qcd_field_tune(qcd_field f, int knob, int value) {
+    if (!f) return set_error(QCD_EINVAL, "null field");
+    switch (knob) {
+        case QCD_TUNE_STENCIL_BLOCK: f->st_block = value ? 1 : 0; break;
+        case QCD_TUNE_STENCIL_RG:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return set_error(QCD_EINVAL, "right-hand sides per site tile must be 0, 1, 2 or 4");
+            f->st_rg = value;
+            break;
+        case QCD_TUNE_STENCIL_ORDER: f->st_order = value ? 1 : 0; break;
+        default: return set_error(QCD_EINVAL, "unknown tuning knob");
+    }
+    ++f->graph_gen;   // captured graphs hold the previous launch choices
+    return 0;
+}
+
+int qcd_workspace_cached(int device, size_t *bytes) {
+    if (!bytes) return set_error(QCD_EINVAL, "null byte count");
+    *bytes = ws_cached_bytes(device);
+    return 0;
+}
+
+int qcd_field_trim(qcd_field f) {
+    if (!f) return set_error(QCD_EINVAL, "null field");
+    if (capturing()) return set_error(QCD_EINVAL, "workspace release during stream capture");
+    DFL_HIP(hipDeviceSynchronize());
+    graph_cache_free(f);
+    ++f->graph_gen;
+    for (int k = 0; k < (int)(sizeof(f->buf) / sizeof(f->buf[0])); ++k) {
+        ws_release(f->device, f->buf[k], f->buf_bytes[k]);
+        f->buf[k] = nullptr;
+        f->buf_bytes[k] = 0;
+    }
+    return 0;
+}
+
+int qcd_workspace_trim(int device) {
+    std::vector<CachedBuf> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (size_t i = 0; i < g_ws_cache.size();)
+            if (device < 0 || g_ws_cache[i].dev == device) {
+                drop.push_back(g_ws_cache[i]);
+                g_ws_cache.erase(g_ws_cache.begin() + i);
+            } else {
+                ++i;
+            }
+    }
+    if (drop.empty()) return 0;
+    int cur = 0;
+    DFL_HIP(hipGetDevice(&cur));
+    for (const CachedBuf &c : drop) {
+        DFL_HIP(hipSetDevice(c.dev));
+        DFL_HIP(hipDeviceSynchronize());
+        DFL_HIP(hipFree(c.p));
+    }
+    DFL_HIP(hipSetDevice(cur));
+    return 0;
+}
+
 int qcd_prof_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
@@ -588,8 +657,7 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         return rc;
     };
 #define ALLOC(ptr, bytes)                                                                        \
-    if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                                    \
-        (void)hipGetLastError();                                                                \
+    if (!dev_alloc(f->device, (void **)&(ptr), (bytes))) {                                      \
         return fail(set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create"));     \
     }
     ALLOC(f->nbr, sizeof(int) * 8 * V);
@@ -636,6 +704,10 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
             }
     }
     if (g.Vbh > 32767) return fail(set_error(QCD_EINVAL, "Schwarz block too large"));
+    // stencil launch defaults, overridable from the environment
+    if (const char *e = getenv("DFL_STENCIL_BLOCK")) f->st_block = atoi(e);
+    if (const char *e = getenv("DFL_STENCIL_RG")) f->st_rg = atoi(e);
+    if (const char *e = getenv("DFL_STENCIL_ORDER")) f->st_order = atoi(e);
     // blocks in lexicographic order -> their place in the colour-major layout
     std::vector<int> bord(g.Nb);
     for (int Bl = 0; Bl < g.Nb; ++Bl) {
@@ -679,10 +751,10 @@ int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream
     for (int m = 0; m < 4; ++m) V *= lat->dims[m] > 0 ? lat->dims[m] : 0;
     if (V <= 0) return set_error(QCD_EINVAL, "lattice extents must be positive");
     double2 *canon = nullptr;
-    if (hipMalloc((void **)&canon, sizeof(double2) * 36 * V) != hipSuccess) {
-        (void)hipGetLastError();
+    int dev = 0;
+    DFL_HIP(hipGetDevice(&dev));
+    if (!dev_alloc(dev, (void **)&canon, sizeof(double2) * 36 * V))
         return set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create");
-    }
     int rc = 0;
     hipError_t e = hipMemcpyAsync(canon, links_host, sizeof(double2) * 36 * V, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) rc = set_error(QCD_EHIP, std::string("upload: ") + hipGetErrorString(e));

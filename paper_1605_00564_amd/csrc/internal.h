@@ -607,6 +607,10 @@ struct qcd_field_s {
     size_t buf_bytes[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
     unsigned graph_gen = 0;  // bumped whenever a scratch buffer moves (captured graphs refer to them)
+    // stencil launch choices (autotuner knobs; defaults from the environment)
+    int st_block = 1;        // block-staged kernel when the block fits (0: site tiles)
+    int st_rg = 0;           // right-hand sides per site tile (0: automatic)
+    int st_order = 1;        // site tiles in lexicographic block order (0: memory order)
     void *graphs = nullptr;  // captured solve graphs (owned; see batched.hip)
     hipStream_t cap = nullptr;  // library stream used for stream capture
     double *hp = nullptr;    // pinned host scratch (4096 doubles)
@@ -635,6 +639,7 @@ void graph_cache_free(qcd_field f);
 int ws_acquire(int dev, size_t bytes, void **p, size_t *got);
 void ws_release(int dev, void *p, size_t bytes);
 size_t ws_cached_bytes(int dev);   // held in the cache, available to new requests
+bool dev_alloc(int dev, void **p, size_t bytes);   // hipMalloc, freeing the cache on failure
 
 // Profiling of kernel classes with HIP events.
 enum ProfClass { PROF_DIRAC = 0, PROF_SAP = 1, PROF_DFL = 2, PROF_LITTLE = 3, PROF_BLAS = 4, PROF_OTHER = 5 };

@@ -173,23 +173,32 @@ def su3_from_gaussian(omega: np.ndarray, eps: float) -> np.ndarray:
     return reunitarise(U)
 
 
-def gauge_field(dims, eps: float, seed: int = 1) -> np.ndarray:
+def gauge_field(dims, eps: float, seed: int = 1, progress=None) -> np.ndarray:
     """Synthetic gauge field U[V, 4, 3, 3] with U = exp(i eps H) per link.
 
     Draw order of the 8 Gaussians: site (lexicographic), then mu, then a.
     Links are periodic in every direction; the fermion boundary phase is
-    not part of the field.
+    not part of the field.  progress(fraction) is called now and then.
     """
+    import threading
     V = volume(dims)
     key = stream_key(seed, STREAM_GAUGE)
     out = np.empty((V, 4, 3, 3), dtype=np.complex128)
     chunk = 1 << 16
+    nchunks = (V + chunk - 1) // chunk
+    done = [0]
+    lock = threading.Lock()
 
     def work(s0):
         s1 = min(V, s0 + chunk)
         j = np.arange(s0 * 32, s1 * 32, dtype=np.uint64)
         om = gaussian(key, j).reshape(s1 - s0, 4, 8)
         out[s0:s1] = su3_from_gaussian(om, eps)
+        if progress is not None:
+            with lock:
+                done[0] += 1
+                if done[0] % 16 == 0:
+                    progress(done[0] / nchunks)
 
     _parallel_chunks(work, range(0, V, chunk))
     return out

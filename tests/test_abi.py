@@ -46,3 +46,26 @@ def test_error_strings_without_a_device():
         assert s and s not in seen, (code, s)
         seen.add(s)
     assert lib.qcd_strerror(-99).decode()
+
+
+def test_autotuner_block_candidates_follow_the_checkerboard_rule():
+    """Block shapes must divide the lattice with an even number of blocks per
+    direction; on 24^3 x 48 that excludes 8^4 (three blocks across 24)."""
+    from paper_1605_00564_amd import tune
+    cands = ((4, 4, 4, 4), (8, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8))
+    assert tune.valid_blocks((48, 24, 24, 24), cands) == [(4, 4, 4, 4), (8, 4, 4, 4), (6, 6, 6, 6)]
+    assert tune.valid_blocks((64, 32, 32, 32), cands) == [(4, 4, 4, 4), (8, 4, 4, 4), (8, 8, 8, 8)]
+    assert tune.valid_blocks((96, 48, 48, 48), cands) == list(cands)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_workspace_cache_calls_without_a_device():
+    """An empty workspace cache answers and trims without touching a device;
+    a null byte count is an argument error."""
+    lib = ctypes.CDLL(LIB)
+    n = ctypes.c_size_t(123)
+    assert lib.qcd_workspace_cached(0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.qcd_workspace_cached(0, None) == -1
+    assert lib.qcd_workspace_trim(-1) == 0
+    lib.qcd_field_trim.argtypes = [ctypes.c_void_p]
+    assert lib.qcd_field_trim(None) == -1

@@ -92,3 +92,60 @@ def test_graph_mode_requires_fixed_iterations():
     assert e.value.code == -1
     d.close()
     fld.close()
+
+
+def test_autotuner_choice_solves():
+    """The autotuner times the valid block shapes (4^4 and 8 x 4^3 here) on
+    a trial batch of 4, picks the outer iteration count per shape, times
+    batch 8 for the winner, then the stencil variants, and returns ready
+    handles.  Solves with its choice report the FP64 residual the oracle
+    recomputes, and flag it against the target."""
+    torch, dfl = _gpu()
+    from paper_1605_00564_amd import tune
+    dims = (16, 8, 8, 8)
+    U = synth.gauge_field(dims, 0.4, 1)
+    choice, fld, d = tune.tune_solver(dims, U, 0.124, 1.5, nsrc=16, batches=(4, 8), Ns=8, ninv=3)
+    assert choice.block in ((4, 4, 4, 4), (8, 4, 4, 4)) and choice.batch in (4, 8)
+    assert [(t["block"], t["batch"]) for t in choice.table][:2] == [((4, 4, 4, 4), 4), ((8, 4, 4, 4), 4)]
+    assert len(choice.table) == 3 and choice.table[2]["batch"] == 8
+    assert 2 <= choice.fixed_iters <= 8 and choice.trial_rel_res <= 0.8 * 3e-3
+    p = tune.sloppy_params(d, choice.fixed_iters)
+    b = list(dfl.z2_sources(fld, seed=5, n=4, dtype=torch.complex128))
+    x, info = dfl.gcr_solve_batched(fld, b, p, batch=choice.batch, graph=True)
+    op = oracle.Operator(dims, U, 0.124, 1.5, -1)
+    for r in range(4):
+        bb = b[r].cpu().numpy()
+        rr = oracle.norm(bb - op.M(x[r].cpu().numpy())) / oracle.norm(bb)
+        assert abs(rr - info[r].rel_res) <= 1e-9 * rr, (r, rr, info[r].rel_res)
+        assert (info[r].status == 0) == (rr <= 3e-3) and rr < 1e-2, (r, rr)
+    d.close()
+    fld.close()
+
+
+def test_workspace_cache_keeps_and_trims_closed_handles_buffers():
+    torch, dfl = _gpu()
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    dfl.workspace_trim()
+    fld, d, p = make(U, torch, dfl)
+    b = sources(torch, dfl, fld)[:4]
+    dfl.gcr_solve_batched(fld, b, p, batch=4, graph=False)
+    outgrown = dfl.workspace_cached(0)     # buffers the handle replaced by larger ones
+    d.close()
+    fld.close()
+    held = dfl.workspace_cached(0)
+    assert held > outgrown
+    # a new handle of the same size takes the cached buffers back
+    fld, d, p = make(U, torch, dfl)
+    x, info = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=False)
+    assert dfl.workspace_cached(0) < held
+    # trimming a live handle gives its buffers back; it allocates again later
+    before = dfl.workspace_cached(0)
+    fld.trim()
+    assert dfl.workspace_cached(0) > before
+    x2, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=False)
+    for r in range(4):
+        assert torch.equal(x2[r], x[r])
+    d.close()
+    fld.close()
+    dfl.workspace_trim(0)
+    assert dfl.workspace_cached(0) == 0

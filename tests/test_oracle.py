@@ -475,3 +475,4 @@ def test_counter_generator_c_matches_python():
     g = synth.gaussian(key, np.arange(2 * 2 * 16 * 12, dtype=np.uint64))
     ref = (g[0::2] + 1j * g[1::2]).reshape(2, 16, 4, 3)
     assert np.abs(got - ref).max() < 1e-14
+
