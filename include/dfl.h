@@ -263,12 +263,18 @@ int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_
  * QCD_TUNE_STENCIL_RG     right-hand sides per site tile: 0 (automatic),
  *                         1, 2 or 4;
  * QCD_TUNE_STENCIL_ORDER  1 = site tiles in lexicographic block order,
- *                         0 = memory order.
+ *                         0 = memory order;
+ * QCD_TUNE_STENCIL_NR     block-staged kernel: right-hand sides per
+ *                         workgroup, sharing each link and clover load:
+ *                         0 (automatic: 2), 1, 2 or 4; reduced to a divisor
+ *                         of the call's count whose staged blocks fit the
+ *                         device's LDS per workgroup (FP16 spinors: 1).
  * Results do not depend on these; graphs captured on the handle are
  * dropped.  Unknown knob or value: QCD_EINVAL. */
 #define QCD_TUNE_STENCIL_BLOCK 0
 #define QCD_TUNE_STENCIL_RG 1
 #define QCD_TUNE_STENCIL_ORDER 2
+#define QCD_TUNE_STENCIL_NR 3
 int qcd_field_tune(qcd_field f, int knob, int value);
 
 /* Process-wide workspace cache.  Scratch buffers that a handle gives up

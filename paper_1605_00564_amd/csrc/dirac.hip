@@ -122,10 +122,18 @@ __device__ inline void gen_spin(const typename Chunk<S>::T *src, long stride, co
     }
 }
 
+// NR right-hand sides per workgroup (NR divides nrhs), Vb x NR threads: a
+// wave holds 64 / NR sites of the block for each of the NR right-hand
+// sides, lane l taking site l % (64 / NR) of the wave's run and right-hand
+// side l / (64 / NR).  Every thread does the one-site, one-right-hand-side
+// work, but the NR lanes of a site read the same link, clover and table
+// entries in the same instruction, so each of those loads fetches the data
+// of 64 / NR sites instead of 64 (NR = 1 is the plain layout).
 // RES: out = b - M in, and the workgroup's share of ||out||^2 into
-// part[rhs][block] (a fixed order of additions, so the norm is reproducible).
+// part[rhs][block in memory] (a fixed order of additions, so the norm is
+// reproducible and independent of the launch order).
 // S: input spinor storage (staged in LDS), SO: output storage.
-template <class S, class SO, class R, int LF, int CF, int MAXT, bool RES = false>
+template <class S, class SO, class R, int LF, int CF, int MAXT, int NR = 1, bool RES = false>
 __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in, void *__restrict__ out,
                                                     const void *__restrict__ U, const void *__restrict__ clo,
                                                     const int *__restrict__ nbr, const short *__restrict__ lnbr,
@@ -136,20 +144,31 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
     constexpr int NCH = Spin<S>::NCH;
     constexpr bool HALF = NCH == 3;
     extern __shared__ unsigned char dsm_raw[];
-    unsigned bx, r;
-    xcd_order(bx, r);
+    unsigned bx, rg;
+    xcd_order(bx, rg);
     const long B = border[bx];
     const int Vb = 2 * Vbh;
-    T *sm = reinterpret_cast<T *>(dsm_raw);
-    float *smsc = reinterpret_cast<float *>(sm + NCH * Vb);  // per-site scales (FP16 storage)
-    const int t = threadIdx.x;
+    constexpr int SPW = 64 / NR;                       // sites per wave
+    const int lane = threadIdx.x & 63, q = lane / SPW;
+    const int t = (threadIdx.x >> 6) * SPW + (lane - q * SPW);   // site in the block
+    // LDS: one block of NCH chunks per site for each right-hand side, then
+    // the per-site scales (FP16 storage)
+    T *sm = reinterpret_cast<T *>(dsm_raw) + q * NCH * Vb;
+    float *smsc = reinterpret_cast<float *>(reinterpret_cast<T *>(dsm_raw) + NR * NCH * Vb) + q * Vb;
     const int par = t >= Vbh ? 1 : 0;
     const int j = t - par * Vbh;
     const unsigned x = (unsigned)(par * Vh + B * Vbh + j);
-    const char *inb = wave_uniform(static_cast<const char *>(in) + (size_t)r * Spin<S>::BYTES * V);
-    char *outb = wave_uniform(static_cast<char *>(out) + (size_t)r * Spin<SO>::BYTES * V);
+    const unsigned xi = x + (unsigned)(q * Spin<S>::NCH * V);     // this lane's input spinor
+    const unsigned xo = x + (unsigned)(q * Spin<SO>::NCH * V);    // and output spinor
+    // buffer bases stay wave-uniform (the first right-hand side of the
+    // workgroup); a lane's own right-hand side enters through its element
+    // index: q x NCH x V 16-byte chunks further (FP32 and FP64 storage only)
+    static_assert(NR == 1 || (Spin<S>::NCH * 16 == Spin<S>::BYTES && Spin<SO>::NCH * 16 == Spin<SO>::BYTES),
+                  "several right-hand sides per workgroup need chunk-only spinor storage");
+    const char *inb = wave_uniform(static_cast<const char *>(in) + (size_t)rg * NR * Spin<S>::BYTES * V);
+    char *outb = wave_uniform(static_cast<char *>(out) + (size_t)rg * NR * Spin<SO>::BYTES * V);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) sm[c * Vb + t] = ld<T>(inb, c, V, x);
+    for (int c = 0; c < NCH; ++c) sm[c * Vb + t] = ld<T>(inb, c, V, xi);
     if constexpr (HALF) smsc[t] = ld<float>(inb, 12, V, x);
     __syncthreads();
     const uint4 nb4 = ld<uint4>(lnbr, 0, 0, (unsigned)t);
@@ -166,7 +185,7 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
     // right index and no boundary sign): a load guarded by the in-block test
     // becomes a branch that costs far more registers than the table read.
     const T *sm_g = sm;
-    const T *in_g = reinterpret_cast<const T *>(inb);
+    const T *in_g = reinterpret_cast<const T *>(inb) + (size_t)q * NCH * V;
     const float *smsc_g = smsc;
     const float *insc_g = reinterpret_cast<const float *>(inb) + 12 * V;
 #define DFL_BLK_HOP(MU)                                                                                 \
@@ -198,8 +217,8 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = rmac(o[k], -kappa, acc[k]);
     if constexpr (RES) {
-        __shared__ double red[MAXT / 64];
-        Spin<S>::load(wave_uniform(static_cast<const char *>(b) + (size_t)r * Spin<S>::BYTES * V), V, x, p);
+        __shared__ double red[NR][MAXT / 64];
+        Spin<S>::load(wave_uniform(static_cast<const char *>(b) + (size_t)rg * NR * Spin<S>::BYTES * V), V, xi, p);
         double nn = 0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -207,16 +226,29 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
             nn = ffma((double)o[k].re, (double)o[k].re, ffma((double)o[k].im, (double)o[k].im, nn));
         }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
-        if ((t & 63) == 0) red[t >> 6] = nn;
+        for (int off = SPW / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+        if (lane == q * SPW) red[q][threadIdx.x >> 6] = nn;
         __syncthreads();
-        if (t == 0) {
+        if (threadIdx.x < NR) {
             double sum = 0;
-            for (int w = 0; w < (Vb + 63) / 64; ++w) sum += red[w];
-            part[(size_t)r * gridDim.x + bx] = sum;
+            for (int w = 0; w < Vb / SPW; ++w) sum += red[threadIdx.x][w];
+            // memory order of the blocks: the same sum for any launch order
+            part[(size_t)(rg * NR + threadIdx.x) * gridDim.x + B] = sum;
         }
     }
-    Spin<SO>::store(outb, V, x, o);
+    Spin<SO>::store(outb, V, xo, o);
+}
+
+// right-hand sides per block-staged workgroup: the handle's choice (0:
+// automatic, 2), reduced until it divides nrhs, the workgroup has at most
+// 1024 threads and 256 per right-hand side, and the staged blocks fit the
+// device's LDS per workgroup
+template <class S, class SO>
+static int blk_nr(qcd_field f, int nrhs, int Vb, size_t lds) {
+    if (Spin<S>::NCH * 16 != Spin<S>::BYTES || Spin<SO>::NCH * 16 != Spin<SO>::BYTES) return 1;   // FP16 storage
+    int nr = f->st_nr > 0 ? f->st_nr : 2;
+    while (nr > 1 && (nrhs % nr || Vb > 256 || (size_t)nr * lds > f->lds_max)) nr /= 2;
+    return nr;
 }
 
 template <class S, class SO, class R, int LF, int CF>
@@ -243,13 +275,23 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     const int Vb = 2 * f->g.Vbh;
     const size_t lds = (size_t)Spin<S>::BYTES * Vb;
     if (f->st_block && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(R) == 4)) {
-        const dim3 grid((unsigned)f->g.Nb, (unsigned)nrhs);
-#define DFL_BLK_LAUNCH(MAXT)                                                                                  \
-    k_dirac_blk<S, SO, R, LF, CF, MAXT><<<grid, Vb, lds, s>>>(in, out, U, C, f->nbr, f->lnbr, f->border, V,      \
-                                                              f->g.Vh, f->g.Vbh, kappa)
-        if (Vb <= 256) DFL_BLK_LAUNCH(256);
-        else if (Vb <= 512) DFL_BLK_LAUNCH(512);
-        else DFL_BLK_LAUNCH(1024);
+        const int nr = blk_nr<S, SO>(f, nrhs, Vb, lds);
+        const dim3 grid((unsigned)f->g.Nb, (unsigned)(nrhs / nr));
+#define DFL_BLK_LAUNCH(MAXT, NR)                                                                              \
+    k_dirac_blk<S, SO, R, LF, CF, MAXT, NR><<<grid, Vb * NR, NR * lds, s>>>(in, out, U, C, f->nbr, f->lnbr,      \
+                                                                        f->border, V, f->g.Vh, f->g.Vbh, kappa)
+        constexpr bool chunked = Spin<S>::NCH * 16 == Spin<S>::BYTES && Spin<SO>::NCH * 16 == Spin<SO>::BYTES;
+        bool launched = false;
+        if constexpr (chunked) {
+            if (nr == 4) DFL_BLK_LAUNCH(1024, 4);
+            if (nr == 2) DFL_BLK_LAUNCH(512, 2);
+            launched = nr > 1;
+        }
+        if (!launched) {
+            if (Vb <= 256) DFL_BLK_LAUNCH(256, 1);
+            else if (Vb <= 512) DFL_BLK_LAUNCH(512, 1);
+            else DFL_BLK_LAUNCH(1024, 1);
+        }
 #undef DFL_BLK_LAUNCH
         DFL_HIP(hipGetLastError());
         return 0;
@@ -291,15 +333,16 @@ int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int
         // bytes: FP64 links and clover once, x, b in and r out per rhs
         ProfScope ps(PROF_DIRAC, s, 1920.0 * g.V * nrhs, g.V * (4 * 144.0 + 576.0 + nrhs * 3 * 192.0),
                      1.0 * g.V * nrhs);
-        const dim3 grid((unsigned)g.Nb, (unsigned)nrhs);
-        if (Vb <= 256)
-            k_dirac_blk<double, double, double, LNK_F64, CLO_F64, 256, true><<<grid, Vb, lds, s>>>(
-                x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh,
-                f->lat.kappa, b, part);
-        else
-            k_dirac_blk<double, double, double, LNK_F64, CLO_F64, 512, true><<<grid, Vb, lds, s>>>(
-                x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh,
-                f->lat.kappa, b, part);
+        const int nr = blk_nr<double, double>(f, nrhs, Vb, lds);
+        const dim3 grid((unsigned)g.Nb, (unsigned)(nrhs / nr));
+#define DFL_RES_LAUNCH(MAXT, NR)                                                                        \
+    k_dirac_blk<double, double, double, LNK_F64, CLO_F64, MAXT, NR, true><<<grid, Vb * NR, NR * lds, s>>>( \
+        x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh, f->lat.kappa, b, part)
+        if (nr == 4) DFL_RES_LAUNCH(1024, 4);
+        else if (nr == 2) DFL_RES_LAUNCH(512, 2);
+        else if (Vb <= 256) DFL_RES_LAUNCH(256, 1);
+        else DFL_RES_LAUNCH(512, 1);
+#undef DFL_RES_LAUNCH
         DFL_HIP(hipGetLastError());
     }
     return blas_reduce(part, 1, g.Nb, nrhs, norm2, s);

@@ -543,6 +543,11 @@ int qcd_field_tune(qcd_field f, int knob, int value) {
             f->st_rg = value;
             break;
         case QCD_TUNE_STENCIL_ORDER: f->st_order = value ? 1 : 0; break;
+        case QCD_TUNE_STENCIL_NR:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return set_error(QCD_EINVAL, "right-hand sides per block workgroup must be 0, 1, 2 or 4");
+            f->st_nr = value;
+            break;
         default: return set_error(QCD_EINVAL, "unknown tuning knob");
     }
     ++f->graph_gen;   // captured graphs hold the previous launch choices
@@ -651,6 +656,11 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     f->lat = *lat;
     f->g = g;
     DFL_HIP(hipGetDevice(&f->device));
+    {
+        int lds = 0;
+        DFL_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, f->device));
+        f->lds_max = lds > 0 ? (size_t)lds : 64 * 1024;
+    }
     const long V = g.V, Vh = g.Vh;
     auto fail = [&](int rc) {
         qcd_field_destroy(f);
@@ -708,6 +718,10 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     if (const char *e = getenv("DFL_STENCIL_BLOCK")) f->st_block = atoi(e);
     if (const char *e = getenv("DFL_STENCIL_RG")) f->st_rg = atoi(e);
     if (const char *e = getenv("DFL_STENCIL_ORDER")) f->st_order = atoi(e);
+    if (const char *e = getenv("DFL_STENCIL_NR")) {
+        const int v = atoi(e);
+        f->st_nr = v == 1 || v == 2 || v == 4 ? v : 0;
+    }
     // blocks in lexicographic order -> their place in the colour-major layout
     std::vector<int> bord(g.Nb);
     for (int Bl = 0; Bl < g.Nb; ++Bl) {
