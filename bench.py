@@ -335,6 +335,8 @@ def main():
     ap.add_argument("--ns", type=int, default=12)
     ap.add_argument("--ninv", type=int, default=5)
     ap.add_argument("--no-deflation", action="store_true")
+    ap.add_argument("--sweep-block-ns", default="",
+                    help="one AMA step per block shape and N_s, e.g. '4,4,4,4:8,12,20;8,4,4,4:8,12,20'")
     ap.add_argument("--sloppy-storage", type=int, default=F16)
     ap.add_argument("--batch", type=int, default=24, help="right-hand sides per solver launch (0: from free memory)")
     ap.add_argument("--little-maxit", type=int, default=16,
@@ -403,7 +405,7 @@ def main():
 
     state = {}
 
-    def step():
+    def step(block=block, ns=args.ns, pos=pos):
         ph = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -412,7 +414,7 @@ def main():
         t1 = time.perf_counter()
         d = None
         if not args.no_deflation:
-            d = dfl.Deflation(fld, Ns=args.ns, ninv=args.ninv, seed=7, sap=sap_sloppy)
+            d = dfl.Deflation(fld, Ns=ns, ninv=args.ninv, seed=7, sap=sap_sloppy)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sap_sloppy, dfl=d, little_tol=1e-6,
@@ -440,6 +442,28 @@ def main():
         log(f"[bench] warmup {w}: {ph}")
         state.pop("dfl", None)
         state.pop("fld", None)
+
+    if args.sweep_block_ns:
+        # one AMA step per (block shape, N_s) on the same gauge field
+        rows = []
+        for bs in args.sweep_block_ns.split(";"):
+            b_txt, ns_txt = bs.split(":")
+            b = tuple(int(v) for v in b_txt.split(","))
+            for ns in (int(v) for v in ns_txt.split(",")):
+                ph = step(block=b, ns=ns, pos=positions(work, b))
+                infs, infe = state.pop("infs"), state.pop("infe")
+                state.pop("dfl", None)
+                state.pop("fld", None)
+                row = {"block": list(b), "Ns": ns, "s_per_source": ph["total"] / npos,
+                       "setup_s": ph["field"] + ph["deflation"], "solves_s": ph["solves"],
+                       "sloppy_iters": [min(i.iters for i in infs), max(i.iters for i in infs)],
+                       "exact_iters": [min(i.iters for i in infe), max(i.iters for i in infe)],
+                       "sloppy_max_rel_res": max(i.rel_res for i in infs),
+                       "exact_max_rel_res": max(i.rel_res for i in infe)}
+                rows.append(row)
+                log("[sweep] " + json.dumps(row))
+        print(json.dumps({"block_ns_sweep": rows, "workload": args.workload, "positions": npos}), flush=True)
+        return
 
     dfl.prof_reset()
     dfl.prof_enable(True)

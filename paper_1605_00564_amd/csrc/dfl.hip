@@ -326,18 +326,31 @@ __global__ void __launch_bounds__(256) k_restrict_mfma64(const double2 *__restri
 // Each thread owns one float4 element (two complex) of a block and PR
 // right-hand sides, so phi is read once per PR vectors.  A workgroup covers
 // one chunk of 256 elements of one block (grid.x = blocks x chunks), so the
-// block's coefficients are uniform and held in scalar registers.
+// block's coefficients are the same for all its threads: they are staged in
+// LDS when they fit (Ns x PR complex), which takes the chain of dependent
+// coefficient loads out of the inner loop.  Sums are FP64 either way.
 constexpr int PR = 12;
-template <class E, int MODE>
+template <class E, int MODE, bool STG>
 __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4 *__restrict__ phi,
                                                  const int *__restrict__ boff, const double2 *__restrict__ cf,
                                                  long V, long Vh, int Vbh, int Ns, int Nb, int n, int nchunk) {
     const int B = blockIdx.x / nchunk;
     const long per = 12L * Vbh;
     const long q = (long)(blockIdx.x - B * nchunk) * 256 + threadIdx.x;
-    if (q >= per) return;
     const int r0 = blockIdx.y * PR;
     const int nr = min(PR, n - r0);
+    // STG: the workgroup's coefficients c[r0 + k][B][l] staged in LDS once
+    // (cs[l][k], zero for k >= nr), read back as broadcasts; otherwise each
+    // is read from global memory where it is used
+    extern __shared__ double2 cs[];
+    if constexpr (STG) {
+        for (int i = threadIdx.x; i < Ns * PR; i += 256) {
+            const int l = i / PR, k = i - l * PR;
+            cs[i] = k < nr ? cf[((size_t)(r0 + k) * Nb + B) * Ns + l] : make_double2(0, 0);
+        }
+        __syncthreads();
+    }
+    if (q >= per) return;
     const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
     const long site = p * Vh + boff[B] + j;
     double ar[PR], ai[PR], br[PR], bi[PR];
@@ -347,8 +360,8 @@ __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4
         const float4 f = phi[((size_t)B * Ns + l) * per + q];
 #pragma unroll
         for (int k = 0; k < PR; ++k)
-            if (k < nr) {
-                const double2 w = cf[((size_t)(r0 + k) * Nb + B) * Ns + l];
+            if (STG || k < nr) {
+                const double2 w = STG ? cs[l * PR + k] : cf[((size_t)(r0 + k) * Nb + B) * Ns + l];
                 ar[k] += f.x * w.x - f.y * w.y;
                 ai[k] += f.x * w.y + f.y * w.x;
                 br[k] += f.z * w.x - f.w * w.y;
@@ -604,8 +617,14 @@ int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
     dfl_work_counts(d, n, (F32V ? 96 : 192) * (MODE == 0 ? 1 : 2), fl, by);
     ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
     const int nchunk = (int)nblocks(12L * g.Vbh, 256);
-    k_prolong<E, MODE><<<dim3((unsigned)(d->Nb * nchunk), (n + PR - 1) / PR), 256, 0, s>>>(
-        v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n, nchunk);
+    const dim3 grid((unsigned)(d->Nb * nchunk), (n + PR - 1) / PR);
+    const size_t stg = sizeof(double2) * (size_t)d->Ns * PR;
+    if (stg <= 48 * 1024)
+        k_prolong<E, MODE, true><<<grid, 256, stg, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n,
+                                                        nchunk);
+    else
+        k_prolong<E, MODE, false><<<grid, 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n,
+                                                       nchunk);
     DFL_HIP(hipGetLastError());
     return 0;
 }
