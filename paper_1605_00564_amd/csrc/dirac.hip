@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
 #undef DFL_BLK_HOP
     cx<R> o[12];
     gen_spin<S, R>(sm_g + t, Vb, smsc_g + t, p);
-    clover_apply<CF, R, true>(clo, V, x, p, o);
+    clover_apply<CF, R, false>(clo, V, x, p, o);
 #pragma unroll
     for (int k = 0; k < 12; ++k) o[k] = rmac(o[k], -kappa, acc[k]);
     if constexpr (RES) {
