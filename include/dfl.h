@@ -268,13 +268,19 @@ int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_
  *                         workgroup, sharing each link and clover load:
  *                         0 (automatic: 2), 1, 2 or 4; reduced to a divisor
  *                         of the call's count whose staged blocks fit the
- *                         device's LDS per workgroup (FP16 spinors: 1).
+ *                         device's LDS per workgroup (FP16 spinors: 1);
+ * QCD_TUNE_STENCIL_LINKLDS FP32 vectors with FP16/BF16 links, at least 16
+ *                         right-hand sides, blocks of at most 256 sites:
+ *                         1 = one workgroup per block keeps the block's
+ *                         links in LDS and loops over the right-hand sides
+ *                         two at a time, 0 = the block-staged kernel above.
  * Results do not depend on these; graphs captured on the handle are
  * dropped.  Unknown knob or value: QCD_EINVAL. */
 #define QCD_TUNE_STENCIL_BLOCK 0
 #define QCD_TUNE_STENCIL_RG 1
 #define QCD_TUNE_STENCIL_ORDER 2
 #define QCD_TUNE_STENCIL_NR 3
+#define QCD_TUNE_STENCIL_LINKLDS 4
 int qcd_field_tune(qcd_field f, int knob, int value);
 
 /* Process-wide workspace cache.  Scratch buffers that a handle gives up

@@ -1,6 +1,7 @@
 // Even-odd ordered Wilson-clover stencil  out = A in - kappa H in  on the
 // full lattice (both parities in one launch), multi right-hand side, and the
 // canonical <-> internal vector conversions.
+#include <type_traits>
 #include "internal.h"
 #include "blas.h"
 
@@ -239,6 +240,108 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
     Spin<SO>::store(outb, V, xo, o);
 }
 
+// Link rows 0-1 of a half-precision reconstruct-12 link from three 8-byte
+// chunks `stride` apart, through a generic pointer (LDS or global memory),
+// and its third row rebuilt
+template <class H4, class R>
+__device__ inline void gen_link(const H4 *src, long stride, cx<R> w[9]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const H4 t = src[c * stride];
+        w[2 * c] = {R(to_f(t.v[0])), R(to_f(t.v[1]))};
+        w[2 * c + 1] = {R(to_f(t.v[2])), R(to_f(t.v[3]))};
+    }
+    rebuild_row2(w);
+}
+
+// Block-staged stencil that keeps the block's links in LDS and loops over
+// all right-hand sides of the call, NR at a time (FP32 vectors, FP16 or BF16
+// reconstruct-12 links, blocks of at most 256 sites).  One workgroup per
+// block: the block's 4 forward links per site are loaded once (24 KB for a
+// 4^4 block) and read from LDS by every group of right-hand sides; the
+// backward hop into the block reads its neighbour's forward link there too,
+// and only backward hops from outside the block read global memory, through
+// the same generic pointer.  Lanes and right-hand sides as in k_dirac_blk.
+template <class H4, int LF, int CF, int NR>
+__global__ void __launch_bounds__(256 * NR) __attribute__((amdgpu_waves_per_eu(4))) k_dirac_blkL(const void *__restrict__ in, void *__restrict__ out,
+                                                         const void *__restrict__ U, const void *__restrict__ clo,
+                                                         const int *__restrict__ nbr, const short *__restrict__ lnbr,
+                                                         const int *__restrict__ border, long V, long Vh, int Vbh,
+                                                         float kappa, int ngroups) {
+    using T = float4;
+    constexpr int NCH = 6;
+    extern __shared__ unsigned char dsm_raw[];
+    unsigned bx, unused;
+    xcd_order(bx, unused);
+    const long B = border[bx];
+    const int Vb = 2 * Vbh;
+    constexpr int SPW = 64 / NR;
+    const int lane = threadIdx.x & 63, q = lane / SPW;
+    const int t0 = (threadIdx.x >> 6) * SPW + (lane - q * SPW);   // site in the block
+    // LDS: links [mu][3 chunks][Vb] (8 B each), then NR blocks of spinors
+    H4 *lk = reinterpret_cast<H4 *>(dsm_raw);
+    T *sm = reinterpret_cast<T *>(dsm_raw + sizeof(H4) * 12 * Vb) + q * NCH * Vb;
+    const int par = t0 >= Vbh ? 1 : 0;
+    const unsigned x0 = (unsigned)(par * Vh + B * Vbh + (t0 - par * Vbh));
+    const int t = t0;
+    const unsigned x = x0;
+    const H4 *Ug = static_cast<const H4 *>(U);
+    for (int k = q; k < 12; k += NR) lk[k * Vb + t] = ld<H4>(Ug, k, V, x);
+    const H4 *lk_g = lk;
+    const T *sm_g = sm;
+    const float *nosc = nullptr;
+    for (int g = 0; g < ngroups; ++g) {
+        // the site indices are made opaque here, so that nothing derived
+        // from them (table entries, addresses) is kept live across groups:
+        // the compiler would otherwise hold all of it in registers
+        unsigned x = x0;
+        int t = t0;
+        asm volatile("" : "+v"(x), "+v"(t));
+        const int obase = t >= Vbh ? 0 : Vbh;   // LDS offset of the other parity
+        const uint4 nb4 = ld<uint4>(lnbr, 0, 0, (unsigned)t);
+        const unsigned nbw[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
+        const unsigned xi = x + (unsigned)(q * NCH * V);
+        const char *inb = wave_uniform(static_cast<const char *>(in) + (size_t)g * NR * 96 * V);
+        char *outb = wave_uniform(static_cast<char *>(out) + (size_t)g * NR * 96 * V);
+        if (g > 0) __syncthreads();   // the previous group's spinors are no longer read
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) sm[c * Vb + t] = ld<T>(inb, c, V, xi);
+        __syncthreads();
+        const T *in_g = reinterpret_cast<const T *>(inb) + (size_t)q * NCH * V;
+        cx<float> acc[12], w[9], p[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+#define DFL_BLKL_HOP(MU)                                                                                \
+    {                                                                                                   \
+        const int lf = (short)(nbw[MU] & 0xffffu);                                                      \
+        const int lb = (short)(nbw[MU] >> 16);                                                          \
+        const int ef = nbr_at(nbr, 2 * MU, V, x);                                                       \
+        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);                                                   \
+        gen_link<H4, float>(lk_g + MU * 3 * Vb + t, Vb, w);                                             \
+        const unsigned yf = nb_index(ef);                                                               \
+        gen_spin<float, float>(lf >= 0 ? sm_g + obase + lf : in_g + yf, lf >= 0 ? Vb : V, nosc, p);     \
+        hop<float, MU, true>(w, p, nb_sign<float>(ef), acc);                                            \
+        const unsigned y = nb_index(eb);                                                                \
+        gen_spin<float, float>(lb >= 0 ? sm_g + obase + lb : in_g + y, lb >= 0 ? Vb : V, nosc, p);      \
+        gen_link<H4, float>(lb >= 0 ? lk_g + MU * 3 * Vb + obase + lb : Ug + (size_t)MU * 3 * V + y,    \
+                            lb >= 0 ? Vb : V, w);                                                       \
+        hop<float, MU, false>(w, p, nb_sign<float>(eb), acc);                                           \
+        __builtin_amdgcn_sched_barrier(0);                                                              \
+    }
+        DFL_BLKL_HOP(0)
+        DFL_BLKL_HOP(1)
+        DFL_BLKL_HOP(2)
+        DFL_BLKL_HOP(3)
+#undef DFL_BLKL_HOP
+        cx<float> o[12];
+        gen_spin<float, float>(sm_g + t, Vb, nosc, p);
+        clover_apply<CF, float, false>(clo, V, x, p, o);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] = rmac(o[k], -kappa, acc[k]);
+        Spin<float>::store(outb, V, x + (unsigned)(q * NCH * V), o);
+    }
+}
+
 // right-hand sides per block-staged workgroup: the handle's choice (0:
 // automatic, 2), reduced until it divides nrhs, the workgroup has at most
 // 1024 threads and 256 per right-hand side, and the staged blocks fit the
@@ -274,6 +377,19 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
     ProfScope ps(PROF_DIRAC, s, fl, by, un);
     const int Vb = 2 * f->g.Vbh;
     const size_t lds = (size_t)Spin<S>::BYTES * Vb;
+    if constexpr (sizeof(S) == 4 && sizeof(SO) == 4 && (LF == LNK_F16 || LF == LNK_BF16)) {
+        // links in LDS, right-hand sides looped within the workgroup
+        using H4 = std::conditional_t<LF == LNK_F16, h4, b4>;
+        const size_t ldsL = sizeof(H4) * 12 * Vb + 2 * lds;
+        // from 16 right-hand sides on (fewer do not amortise the link staging)
+        if (f->st_block && f->st_linklds && nrhs >= 16 && Vb % 64 == 0 && Vb <= 256 && nrhs % 2 == 0 &&
+            ldsL <= f->lds_max) {
+            k_dirac_blkL<H4, LF, CF, 2><<<dim3((unsigned)f->g.Nb), Vb * 2, ldsL, s>>>(
+                in, out, U, C, f->nbr, f->lnbr, f->border, V, f->g.Vh, f->g.Vbh, (float)kappa, nrhs / 2);
+            DFL_HIP(hipGetLastError());
+            return 0;
+        }
+    }
     if (f->st_block && Vb % 64 == 0 && Vb <= 1024 && lds <= 64 * 1024 && (Vb <= 512 || sizeof(R) == 4)) {
         const int nr = blk_nr<S, SO>(f, nrhs, Vb, lds);
         const dim3 grid((unsigned)f->g.Nb, (unsigned)(nrhs / nr));

@@ -12,8 +12,9 @@ Four choices are made by measurement on the device, never by formula:
 * the number of right-hand sides per solver launch, among the candidates
   that fit the device memory;
 * the Dirac stencil's launch variant (block-staged with 1, 2 or 4
-  right-hand sides per workgroup, or site tiles with 1, 2 or 4 per tile),
-  timed at the chosen batch and set on the handle.
+  right-hand sides per workgroup, or with the block's links held in LDS, or
+  site tiles with 1, 2 or 4 per tile), timed at the chosen batch and set on
+  the handle.
 
 The trial solves use Z2-noise sources built on the device and replay a
 captured graph, as the production sloppy solves do.  Timings are wall-clock
@@ -48,27 +49,29 @@ def _sync():
 def tune_stencil(fld: L.Field, nrhs: int, storage: int = F16, reps: int = 5):
     """Time the stencil variants on nrhs vectors; set and return the fastest.
     A variant is (block-staged, right-hand sides per site tile, right-hand
-    sides per block workgroup)."""
+    sides per block workgroup, links held in LDS)."""
     import torch
     x = torch.randn((nrhs, fld.V, 4, 3), dtype=torch.complex64, device="cuda")
     y = torch.empty_like(x)
-    variants = [(1, 0, 1), (1, 0, 2), (1, 0, 4), (0, 1, 0), (0, 2, 0), (0, 4, 0)]
+    variants = [(1, 0, 1, 0), (1, 0, 2, 0), (1, 0, 4, 0), (1, 0, 2, 1), (0, 1, 0, 0), (0, 2, 0, 0), (0, 4, 0, 0)]
     times = {}
-    for blk, rg, nr in variants:
+    for blk, rg, nr, llds in variants:
         fld.tune(L.Field.TUNE_STENCIL_BLOCK, blk)
         fld.tune(L.Field.TUNE_STENCIL_RG, rg)
         fld.tune(L.Field.TUNE_STENCIL_NR, nr)
+        fld.tune(L.Field.TUNE_STENCIL_LINKLDS, llds)
         L.dirac_apply(fld, x, storage=storage, out=y)
         _sync()
         t = time.perf_counter()
         for _ in range(reps):
             L.dirac_apply(fld, x, storage=storage, out=y)
         _sync()
-        times[(blk, rg, nr)] = (time.perf_counter() - t) / reps
+        times[(blk, rg, nr, llds)] = (time.perf_counter() - t) / reps
     best = min(times, key=times.get)
     fld.tune(L.Field.TUNE_STENCIL_BLOCK, best[0])
     fld.tune(L.Field.TUNE_STENCIL_RG, best[1])
     fld.tune(L.Field.TUNE_STENCIL_NR, best[2])
+    fld.tune(L.Field.TUNE_STENCIL_LINKLDS, best[3])
     return best, times
 
 
@@ -172,7 +175,7 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
             if best is not None:
                 best[3].close()
                 best[2].close()
-            best = (cost, Choice(b, nb, iters, (1, 0, 0), setup, per, worst), fld, d)
+            best = (cost, Choice(b, nb, iters, (1, 0, 0, 1), setup, per, worst), fld, d)
         else:
             d.close()
             fld.close()

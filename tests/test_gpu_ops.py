@@ -94,20 +94,24 @@ def test_dirac_reduced_precision_matches_quantised_oracle(key, storage):
 @pytest.mark.parametrize("storage", [F64, F32, F16])
 def test_dirac_launch_variants_agree_bit_for_bit(storage):
     """The block-staged stencil with 1, 2 or 4 right-hand sides per
-    workgroup does the same arithmetic per site whatever the lane mapping:
-    outputs are identical (so are the site-tile kernel's with 1, 2 or 4 per
-    tile), the two kernels agree to rounding, and both match the oracle.
-    8 right-hand sides on 4^4 blocks; FP64 stays at one per workgroup (LDS)."""
+    workgroup, and (FP16 links) the variant holding the block's links in LDS,
+    do the same arithmetic per site whatever the lane mapping: outputs are
+    identical (so are the site-tile kernel's with 1, 2 or 4 per tile), the
+    two kernels agree to rounding, and both match the oracle.  16 right-hand
+    sides on 4^4 blocks; FP64 uses at most 2 per workgroup (LDS)."""
     torch, dfl = _gpu()
     c = case(*MID)
     dt = np.complex128 if storage == F64 else np.complex64
-    x = torch.from_numpy(synth.gaussian_spinor(c.dims, 8, 1003).astype(dt)).cuda()
+    x = torch.from_numpy(synth.gaussian_spinor(c.dims, 16, 1003).astype(dt)).cuda()
     F = dfl.Field
     outs = {}
     try:
+        c.field.tune(F.TUNE_STENCIL_LINKLDS, 0)
         for nr in (1, 2, 4):
             c.field.tune(F.TUNE_STENCIL_NR, nr)
             outs[("blk", nr)] = dfl.dirac_apply(c.field, x, storage=storage)
+        c.field.tune(F.TUNE_STENCIL_LINKLDS, 1)      # FP16 links: block's links held in LDS
+        outs[("blk", "links in LDS")] = dfl.dirac_apply(c.field, x, storage=storage)
         c.field.tune(F.TUNE_STENCIL_BLOCK, 0)
         for rg in (1, 2, 4):
             c.field.tune(F.TUNE_STENCIL_RG, rg)
@@ -116,6 +120,7 @@ def test_dirac_launch_variants_agree_bit_for_bit(storage):
         c.field.tune(F.TUNE_STENCIL_BLOCK, 1)
         c.field.tune(F.TUNE_STENCIL_RG, 0)
         c.field.tune(F.TUNE_STENCIL_NR, 0)
+        c.field.tune(F.TUNE_STENCIL_LINKLDS, 1)
     ref = outs[("blk", 1)]
     for k, y in outs.items():
         if k[0] == "blk":
@@ -125,7 +130,7 @@ def test_dirac_launch_variants_agree_bit_for_bit(storage):
             d = float((y - ref).abs().max() / ref.abs().max())
             assert d <= (1e-14 if storage == F64 else 1e-6), (k, d)
     qref = (c.op if storage == F64 else c.qop(storage)).M(x.cpu().numpy().astype(np.complex128))
-    for r in range(8):
+    for r in range(16):
         assert rel(ref[r].cpu().numpy(), qref[r]) <= (1e-12 if storage == F64 else 1e-5), r
 
 
