@@ -293,7 +293,9 @@ def run_multi(args, log):
     """Three gauge fields with 8, 32 and 64 sources (half Z2 noise built on
     the device, half point sources), every eighth also solved exactly.  Per
     field the autotuner picks the Schwarz/deflation block shape, the
-    right-hand sides per launch and the stencil variant; the sloppy solves
+    right-hand sides per launch and the stencil variant (from the second
+    field on it times only the two shapes the earlier fields ranked best per
+    site); the sloppy solves
     run the tuned fixed N_iter replayed from captured graphs, and any whose
     FP64 residual is still above 3e-3 is solved again with the
     residual-stopping solver; the exact ones go to 1e-10.  Timed per field:
@@ -304,6 +306,7 @@ def run_multi(args, log):
     from paper_1605_00564_amd import tune
     rows = []
     total_src, total_s = 0, 0.0
+    prior = None
     for dims, seed, nsrc in MULTI_FIELDS:
         t = time.perf_counter()
         U = synth.gauge_field(dims, 0.4, seed, progress=lambda f: log(f"[multi] {dims}: gauge field {100 * f:.0f}%"))
@@ -312,7 +315,9 @@ def run_multi(args, log):
         log(f"[multi] {dims}: gauge field generated in {time.perf_counter() - t:.1f} s")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        choice, fld, d = tune.tune_solver(dims, Ud, 0.124, 1.5, nsrc, fixed_iters=3, log=log)
+        # the smaller fields' tuning ranks the block shapes for the next one
+        choice, fld, d = tune.tune_solver(dims, Ud, 0.124, 1.5, nsrc, fixed_iters=3, prior=prior, log=log)
+        prior = (prior or []) + choice.table
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sap16, sap32 = dfl.SapParams(5, 4, F16), dfl.SapParams(5, 4, F32)

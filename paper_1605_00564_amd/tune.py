@@ -119,9 +119,20 @@ def _trial(fld, d, srcs, nb, iters, res):
     return (time.perf_counter() - t) / nb, max(i.rel_res for i in info)
 
 
+def rank_by_prior(cands, prior):
+    """Order candidate block shapes by a previous tuning's time per source
+    per site (shapes it did not time go last, in their given order)."""
+    seen = {}
+    for row in prior or []:
+        b = tuple(row["block"])
+        v = row["per_source_s"] / row["volume"]
+        seen[b] = min(v, seen.get(b, v))
+    return sorted(cands, key=lambda b: (b not in seen, seen.get(b, 0.0)))
+
+
 def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8)),
                 batches=(8, 12, 16, 24), Ns=12, ninv=5, fixed_iters=2, res=3e-3, margin=0.8, max_iters=8,
-                log=None):
+                prior=None, keep=2, log=None):
     """Pick block shape, outer iteration count and batch for a field with
     nsrc sloppy sources; returns (Choice, field handle, deflation handle) for
     the winner, the handles ready to use (the others are closed).
@@ -132,7 +143,12 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
     candidate's setup has been paid by the time the choice is made, so the
     shape with the least time per source wins (its remaining cost is
     nsrc x that time); setup times are reported, not ranked.  For the winner
-    alone the other batch sizes are timed, then the stencil variant."""
+    alone the other batch sizes are timed, then the stencil variant.
+
+    prior: the table of an earlier tuning with the same kappa, c_sw and
+    field recipe (another lattice size).  Its ranking (time per source per
+    site) orders the valid shapes, only the best `keep` of them are timed,
+    and the search for N_iter starts at the prior winner's count."""
     log = log or (lambda *a: None)
     sap = L.SapParams(5, 4, F16)
     V = 1
@@ -141,6 +157,12 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
     cands = valid_blocks(dims, blocks)
     if not cands:
         raise ValueError(f"no valid block shape for {dims}")
+    if prior:
+        cands = rank_by_prior(cands, prior)[:max(1, keep)]
+        known = [r for r in prior if "fixed_iters" in r]
+        if known:
+            best_prior = min(known, key=lambda r: r["per_source_s"] / r["volume"])
+            fixed_iters = max(fixed_iters, int(best_prior["fixed_iters"]) - 1)
     best = None
     table = []
     nb = None
@@ -168,7 +190,7 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
         fld.trim()
         cost = nsrc * per
         table.append({"block": b, "batch": nb, "fixed_iters": iters, "setup_s": setup, "per_source_s": per,
-                      "trial_rel_res": worst, "solve_cost_s": cost})
+                      "trial_rel_res": worst, "solve_cost_s": cost, "volume": V})
         log(f"[tune] block {b} batch {nb} N_iter {iters}: setup {setup:.2f} s, {per * 1e3:.1f} ms/source, "
             f"residual {worst:.2e}, solve cost {cost:.2f} s")
         if best is None or cost < best[0]:
@@ -187,7 +209,7 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
         del srcs
         table.append({"block": choice.block, "batch": nb, "fixed_iters": choice.fixed_iters,
                       "setup_s": choice.setup_s, "per_source_s": per, "trial_rel_res": worst,
-                      "solve_cost_s": nsrc * per})
+                      "solve_cost_s": nsrc * per, "volume": V})
         log(f"[tune] block {choice.block} batch {nb}: {per * 1e3:.1f} ms/source")
         if per < choice.per_source_s and worst <= margin * res:
             choice.batch, choice.per_source_s, choice.trial_rel_res = nb, per, worst

@@ -69,3 +69,16 @@ def test_workspace_cache_calls_without_a_device():
     assert lib.qcd_workspace_trim(-1) == 0
     lib.qcd_field_trim.argtypes = [ctypes.c_void_p]
     assert lib.qcd_field_trim(None) == -1
+
+
+def test_autotuner_prior_ranks_block_shapes_per_site():
+    """A previous tuning's table (another lattice) orders the candidates by
+    time per source per site; shapes it never timed go last."""
+    from paper_1605_00564_amd import tune
+    prior = [{"block": (4, 4, 4, 4), "per_source_s": 8.0, "volume": 100},
+             {"block": (8, 4, 4, 4), "per_source_s": 5.4, "volume": 100},
+             {"block": (6, 6, 6, 6), "per_source_s": 30.0, "volume": 400},
+             {"block": (8, 4, 4, 4), "per_source_s": 6.0, "volume": 100}]
+    cands = [(4, 4, 4, 4), (8, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8)]
+    assert tune.rank_by_prior(cands, prior) == [(8, 4, 4, 4), (6, 6, 6, 6), (4, 4, 4, 4), (8, 8, 8, 8)]
+    assert tune.rank_by_prior(cands, None) == cands

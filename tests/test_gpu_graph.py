@@ -149,3 +149,18 @@ def test_workspace_cache_keeps_and_trims_closed_handles_buffers():
     fld.close()
     dfl.workspace_trim(0)
     assert dfl.workspace_cached(0) == 0
+
+
+def test_stencil_knobs_reject_bad_values():
+    torch, dfl = _gpu()
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    fld = dfl.Field(DIMS, BLOCK, 0.124, 1.5, U)
+    F = dfl.Field
+    for knob, value in ((F.TUNE_STENCIL_RG, 3), (F.TUNE_STENCIL_NR, 3), (99, 1)):
+        with pytest.raises(dfl.DflError) as e:
+            fld.tune(knob, value)
+        assert e.value.code == -1
+    for knob, value in ((F.TUNE_STENCIL_RG, 4), (F.TUNE_STENCIL_NR, 4), (F.TUNE_STENCIL_LINKLDS, 0),
+                        (F.TUNE_STENCIL_ORDER, 0), (F.TUNE_STENCIL_BLOCK, 1)):
+        fld.tune(knob, value)
+    fld.close()
