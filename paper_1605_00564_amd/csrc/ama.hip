@@ -76,10 +76,14 @@ int solve_set(qcd_field f, const qcd_gcr &p, const std::vector<int> &lex_sc, voi
         const int rc = gcr_internal(f, &p, b64, x64, n, info ? info + r0 : nullptr, s);
         if (rc < 0) return rc;
         if (rc == QCD_NOCONV) status = QCD_NOCONV;
-        for (int r = 0; r < n; ++r) {
+        // a position's spin-colour solutions are contiguous in its output:
+        // one unpack per run of them
+        for (int r = 0; r < n;) {
             const int g = (r0 + r) / 12, sc = (r0 + r) % 12;
+            const int run = std::min(12 - sc, n - r);
             char *dst = static_cast<char *>(outs[g]) + sc * cbytes;
-            DFL_TRY(unpack_spinor(f, x64 + (size_t)r * 12 * V, QCD_F64, dst, io, 1, s));
+            DFL_TRY(unpack_spinor(f, x64 + (size_t)r * 12 * V, QCD_F64, dst, io, run, s));
+            r += run;
         }
     }
     return 0;

@@ -793,7 +793,7 @@ void dfl_free(qcd_dfl d) {
 
 }  // namespace
 
-int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int maxit, hipStream_t s) {
+int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int maxit, bool set, hipStream_t s) {
     const size_t nv = (size_t)d->Nb * d->Ns * n;
     void *p;
     DFL_TRY(field_buffer(d->f, BUF_DFL, 2 * nv * sizeof(double2), &p));
@@ -802,7 +802,7 @@ int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int
     // polled to tol, except without host synchronisation (fixed budget)
     int rc = little_solve(d, u, c, n, tol, maxit, !nosync(), nullptr, nullptr, s);
     if (rc < 0) return rc;
-    return prolong_v<double2, 2>(d, x, c, n, s);
+    return set ? prolong_v<double2, 0>(d, x, c, n, s) : prolong_v<double2, 2>(d, x, c, n, s);
 }
 
 int dfl_project_R(qcd_dfl d, void *z, void *tmp, int n, qcd_prec vec, qcd_prec storage, int maxit, hipStream_t s) {

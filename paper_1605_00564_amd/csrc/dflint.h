@@ -27,7 +27,8 @@ namespace dfl {
 qcd_field dfl_field(qcd_dfl d);
 // x += Phi A^{-1} Phi^+ b for FP64 internal vectors; the little system is
 // solved to relative residual tol (at most maxit iterations)
-int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int maxit, hipStream_t s);
+// x += Phi A^{-1} Phi^+ b (set: x = ...)
+int dfl_low_mode(qcd_dfl d, const double2 *b, double2 *x, int n, double tol, int maxit, bool set, hipStream_t s);
 // z <- P_R z = z - Phi A^{-1} Phi^+ M z, vectors of precision vec (F32 or F64); tmp is n vectors of
 // scratch; the little system gets a fixed budget of maxit iterations (no host synchronisation)
 int dfl_project_R(qcd_dfl d, void *z, void *tmp, int n, qcd_prec vec, qcd_prec storage, int maxit,

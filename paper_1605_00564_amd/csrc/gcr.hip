@@ -92,18 +92,31 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         bn[i] = std::sqrt(h[i]);
     }
 
+    auto converged = [&](const std::vector<double> &res) {
+        for (int i = 0; i < n; ++i)
+            if (res[i] > p->res * bn[i]) return false;
+        return true;
+    };
     // initial guess x = 0, r = b
     std::vector<double> rn(n);
-    DFL_TRY(blas_zero(x, ne64, n, s));
-    DFL_HIP(hipMemcpyAsync(r, b, sizeof(double2) * ne64 * n, hipMemcpyDeviceToDevice, s));
     rn = bn;
+    bool done = p->fixed_iters <= 0 && converged(rn);
+    // with deflation the first low-mode correction reads b and writes x
+    // itself, so x = 0 and r = b need not be stored
+    bool x_zero = p->dfl && !done;
+    if (!x_zero) {
+        DFL_TRY(blas_zero(x, ne64, n, s));
+        DFL_HIP(hipMemcpyAsync(r, b, sizeof(double2) * ne64 * n, hipMemcpyDeviceToDevice, s));
+    }
     // With deflation every cycle starts with the low-mode correction
     // x += Phi A^{-1} Phi^+ r (eq. deflsoln applied to the current residual):
     // the search directions M P_R z = P_L M z only span range(P_L), so the
     // part of r outside it, left by inexact little solves and FP32 rounding,
     // is removed here, in FP64, before the next cycle.
     auto low_mode_correction = [&]() -> int {
-        DFL_TRY(dfl_low_mode(p->dfl, r, x, n, p->little_tol, ns ? p->little_maxit : std::max(p->little_maxit, 200), s));
+        DFL_TRY(dfl_low_mode(p->dfl, x_zero ? b : r, x, n, p->little_tol,
+                             ns ? p->little_maxit : std::max(p->little_maxit, 200), x_zero, s));
+        x_zero = false;
         DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
         if (ns) return 0;
         DFL_TRY(fetch(f, sc.red, n, s, h));
@@ -111,11 +124,6 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         return 0;
     };
 
-    auto converged = [&](const std::vector<double> &res) {
-        for (int i = 0; i < n; ++i)
-            if (res[i] > p->res * bn[i]) return false;
-        return true;
-    };
     const int limit = p->fixed_iters > 0 ? p->fixed_iters : p->nmx;
     // A cycle ends once its residual has dropped by inner_rel: with FP32
     // Krylov vectors that is their precision limit; with deflation (in
@@ -124,7 +132,6 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     // search directions cannot reach.
     const double inner_rel = (vin == QCD_F64 && !p->dfl) ? 0.0 : 1e-6;
     int iters = 0;
-    bool done = p->fixed_iters <= 0 && converged(rn);
     while (!done && iters < limit) {
         if (p->dfl) {
             DFL_TRY(low_mode_correction());
