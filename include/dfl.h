@@ -273,14 +273,21 @@ int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_
  *                         right-hand sides, blocks of at most 256 sites:
  *                         1 = one workgroup per block keeps the block's
  *                         links in LDS and loops over the right-hand sides
- *                         two at a time, 0 = the block-staged kernel above.
- * Results do not depend on these; graphs captured on the handle are
- * dropped.  Unknown knob or value: QCD_EINVAL. */
+ *                         two at a time, 0 = the block-staged kernel above;
+ * QCD_TUNE_SAP_PAIR       Schwarz sweeps with FP32 arithmetic on blocks of
+ *                         128 sites per parity (4^4) and an even number of
+ *                         right-hand sides: 1 = two right-hand sides per
+ *                         workgroup, sharing link and clover loads (the
+ *                         block reductions then add in another order), 0 =
+ *                         one.
+ * Results do not depend on these beyond rounding; graphs captured on the
+ * handle are dropped.  Unknown knob or value: QCD_EINVAL. */
 #define QCD_TUNE_STENCIL_BLOCK 0
 #define QCD_TUNE_STENCIL_RG 1
 #define QCD_TUNE_STENCIL_ORDER 2
 #define QCD_TUNE_STENCIL_NR 3
 #define QCD_TUNE_STENCIL_LINKLDS 4
+#define QCD_TUNE_SAP_PAIR 5
 int qcd_field_tune(qcd_field f, int knob, int value);
 
 /* Process-wide workspace cache.  Scratch buffers that a handle gives up

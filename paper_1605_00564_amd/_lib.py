@@ -219,6 +219,7 @@ class Field:
         self.kappa, self.csw, self.bc_t = float(kappa), float(csw), int(bc_t)
 
     TUNE_STENCIL_BLOCK, TUNE_STENCIL_RG, TUNE_STENCIL_ORDER, TUNE_STENCIL_NR, TUNE_STENCIL_LINKLDS = 0, 1, 2, 3, 4
+    TUNE_SAP_PAIR = 5
 
     def tune(self, knob: int, value: int):
         """Set a launch choice of the Dirac stencil (see include/dfl.h)."""

@@ -544,6 +544,7 @@ int qcd_field_tune(qcd_field f, int knob, int value) {
             break;
         case QCD_TUNE_STENCIL_ORDER: f->st_order = value ? 1 : 0; break;
         case QCD_TUNE_STENCIL_LINKLDS: f->st_linklds = value ? 1 : 0; break;
+        case QCD_TUNE_SAP_PAIR: f->st_sap_pair = value ? 1 : 0; break;
         case QCD_TUNE_STENCIL_NR:
             if (value != 0 && value != 1 && value != 2 && value != 4)
                 return set_error(QCD_EINVAL, "right-hand sides per block workgroup must be 0, 1, 2 or 4");
@@ -720,6 +721,7 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     if (const char *e = getenv("DFL_STENCIL_RG")) f->st_rg = atoi(e);
     if (const char *e = getenv("DFL_STENCIL_ORDER")) f->st_order = atoi(e);
     if (const char *e = getenv("DFL_STENCIL_LINKLDS")) f->st_linklds = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("DFL_SAP_PAIR")) f->st_sap_pair = atoi(e) ? 1 : 0;
     if (const char *e = getenv("DFL_STENCIL_NR")) {
         const int v = atoi(e);
         f->st_nr = v == 1 || v == 2 || v == 4 ? v : 0;

@@ -613,6 +613,7 @@ struct qcd_field_s {
     int st_order = 1;        // site tiles in lexicographic block order (0: memory order)
     int st_nr = 0;           // block-staged kernel: right-hand sides per workgroup (0: automatic)
     int st_linklds = 1;      // FP32 vectors, half links, >= 16 rhs: links in LDS, rhs looped
+    int st_sap_pair = 1;     // Schwarz sweep: two right-hand sides per workgroup (4^4 blocks)
     size_t lds_max = 64 * 1024;   // the device's LDS bytes per workgroup
     void *graphs = nullptr;  // captured solve graphs (owned; see batched.hip)
     hipStream_t cap = nullptr;  // library stream used for stream capture

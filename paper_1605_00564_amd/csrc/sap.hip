@@ -15,10 +15,11 @@
 
 namespace dfl {
 
-template <class R>
+// sum over aligned groups of G lanes (G = 64: the whole wave)
+template <int G = 64, class R>
 __device__ inline R wave_sum(R v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
@@ -63,7 +64,7 @@ __device__ inline void block_hop(const void *U, const short *lnbr, long V, long 
 // (M psi)(x) with the full neighbourhood (neighbours read from global psi)
 template <class S, class R, int LF, int CF>
 __device__ inline void full_dirac_site(const void *psi, const void *U, const void *clo, const int *nbr, long V,
-                                       long x, R kappa, cx<R> out[12]) {
+                                       long x, R kappa, cx<R> out[12], unsigned qoff = 0) {
     cx<R> acc[12], w[9], p[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
@@ -71,11 +72,11 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
     {                                                         \
         const int ef = nbr_at(nbr, 2 * MU, V, x);                 \
         Link<LF>::load(U, V, MU, x, w);                       \
-        Spin<S>::load(psi, V, nb_index(ef), p);               \
+        Spin<S>::load(psi, V, nb_index(ef) + qoff, p);        \
         hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);          \
         const int eb = nbr_at(nbr, 2 * MU + 1, V, x);             \
         Link<LF>::load(U, V, MU, nb_index(eb), w);            \
-        Spin<S>::load(psi, V, nb_index(eb), p);               \
+        Spin<S>::load(psi, V, nb_index(eb) + qoff, p);        \
         hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);         \
     }
     DFL_FHOP(0)
@@ -83,7 +84,7 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
     DFL_FHOP(2)
     DFL_FHOP(3)
 #undef DFL_FHOP
-    Spin<S>::load(psi, V, x, p);
+    Spin<S>::load(psi, V, x + qoff, p);
     clover_apply<CF>(clo, V, x, p, out);
 #pragma unroll
     for (int k = 0; k < 12; ++k) out[k] = rmac(out[k], -kappa, acc[k]);
@@ -92,27 +93,38 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
 // VBHC > 0: the block's sites per parity as a compile-time constant (the
 // component planes of the exchange buffers then sit at immediate LDS
 // offsets); 0: taken from the argument.
-template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0>
+// NR = 2 (FP32 vectors in LDS, KS = 1): a workgroup takes two right-hand
+// sides of its block, each wave 64 / NR sites for both, so the two lanes of
+// a site read the same links and clover entries in one instruction.  Every
+// thread still does one site pair of one right-hand side; the vector bases
+// stay wave-uniform and a lane's right-hand side enters through its element
+// index (qr x NCH x V chunks further).
+template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0, int NR = 1>
 __global__ void __launch_bounds__(MAXT)
     k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, const void *__restrict__ U,
                 const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr,
                 const short *__restrict__ lnbr, long V, long Vh, int Vbh_arg, int nbc, int colour, R kappa, int nmr,
                 int first, cx<R> *gbuf) {
+    static_assert(NR == 1 || (LDS && KS == 1 && Spin<S>::NCH * 16 == Spin<S>::BYTES), "NR = 2 layout");
+    constexpr int SPW = 64 / NR;   // sites per wave
     const int Vbh = VBHC > 0 ? VBHC : Vbh_arg;
     extern __shared__ unsigned char dsm[];
-    __shared__ R red[16][3];
-    const int NT = blockDim.x;
-    const int tid = threadIdx.x;
-    unsigned bx, rhs;
-    xcd_order(bx, rhs);
+    __shared__ R red[16][NR][3];
+    const int lane = threadIdx.x & 63, qr = NR > 1 ? lane / SPW : 0;   // this lane's right-hand side
+    const int NT = blockDim.x / NR;                                       // sites per sweep of the workgroup
+    const int tid = NR > 1 ? (int)(threadIdx.x >> 6) * SPW + (lane - qr * SPW) : (int)threadIdx.x;
+    unsigned bx, rg;
+    xcd_order(bx, rg);
+    const unsigned rhs = rg * NR + qr;
     const size_t fs = (size_t)Spin<S>::BYTES * V;
-    const void *eta = wave_uniform(static_cast<const char *>(eta_all) + rhs * fs);
-    void *psi = wave_uniform(static_cast<char *>(psi_all) + rhs * fs);
+    const void *eta = wave_uniform(static_cast<const char *>(eta_all) + (size_t)rg * NR * fs);
+    void *psi = wave_uniform(static_cast<char *>(psi_all) + (size_t)rg * NR * fs);
+    const unsigned qoff = (unsigned)(qr * Spin<S>::NCH * V);  // its offset, in chunks
     const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
     cx<R> *Rb, *Tb;
     if (LDS) {
-        Rb = reinterpret_cast<cx<R> *>(dsm);
+        Rb = reinterpret_cast<cx<R> *>(dsm) + (size_t)qr * 24 * Vbh;
     } else {
         Rb = gbuf + ((size_t)rhs * gridDim.x + bx) * (size_t)24 * Vbh;
     }
@@ -126,17 +138,17 @@ __global__ void __launch_bounds__(MAXT)
         if (j < Vbh) {
             const long xe_i = boff + j, xo_i = Vh + boff + j;
             cx<R> e[12], m[12];
-            Spin<S>::load(eta, V, xe_i, e);
+            Spin<S>::load(eta, V, xe_i + qoff, e);
             if (!first) {
-                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xe_i, kappa, m);
+                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xe_i, kappa, m, qoff);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
             }
 #pragma unroll
             for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = e[c];
-            Spin<S>::load(eta, V, xo_i, e);
+            Spin<S>::load(eta, V, xo_i + qoff, e);
             if (!first) {
-                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xo_i, kappa, m);
+                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xo_i, kappa, m, qoff);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
             }
@@ -165,11 +177,11 @@ __global__ void __launch_bounds__(MAXT)
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = Tb[c * Vbh + j];
             } else {
-                Spin<S>::load(psi, V, xo_i, q);
+                Spin<S>::load(psi, V, xo_i + qoff, q);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = q[c] + Tb[c * Vbh + j];
             }
-            Spin<S>::store(psi, V, xo_i, q);
+            Spin<S>::store(psi, V, xo_i + qoff, q);
         }
     }
     __syncthreads();
@@ -211,21 +223,21 @@ __global__ void __launch_bounds__(MAXT)
                 }
             }
         }
-        pr_re = wave_sum(pr_re);
-        pr_im = wave_sum(pr_im);
-        pp = wave_sum(pp);
-        if ((tid & 63) == 0) {
-            red[tid >> 6][0] = pr_re;
-            red[tid >> 6][1] = pr_im;
-            red[tid >> 6][2] = pp;
+        pr_re = wave_sum<SPW>(pr_re);
+        pr_im = wave_sum<SPW>(pr_im);
+        pp = wave_sum<SPW>(pp);
+        if (lane == qr * SPW) {
+            red[threadIdx.x >> 6][qr][0] = pr_re;
+            red[threadIdx.x >> 6][qr][1] = pr_im;
+            red[threadIdx.x >> 6][qr][2] = pp;
         }
         __syncthreads();
         R s0 = 0, s1 = 0, s2 = 0;
-        const int nw = (NT + 63) >> 6;
+        const int nw = (blockDim.x + 63) >> 6;
         for (int w = 0; w < nw; ++w) {
-            s0 += red[w][0];
-            s1 += red[w][1];
-            s2 += red[w][2];
+            s0 += red[w][qr][0];
+            s1 += red[w][qr][1];
+            s2 += red[w][qr][2];
         }
         const cx<R> alpha = s2 > R(0) ? cx<R>{s0 / s2, s1 / s2} : cx<R>{R(0), R(0)};
 #pragma unroll
@@ -262,17 +274,17 @@ __global__ void __launch_bounds__(MAXT)
             cx<R> acc[12], t[12], q[12];
             block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
             clover_apply<CF>(cinv, Vh, boff + j, acc, t);
-            Spin<S>::load(psi, V, xo_i, q);
+            Spin<S>::load(psi, V, xo_i + qoff, q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);
-            Spin<S>::store(psi, V, xo_i, q);
+            Spin<S>::store(psi, V, xo_i + qoff, q);
             if (first) {
-                Spin<S>::store(psi, V, xe_i, xe[k]);
+                Spin<S>::store(psi, V, xe_i + qoff, xe[k]);
             } else {
-                Spin<S>::load(psi, V, xe_i, q);
+                Spin<S>::load(psi, V, xe_i + qoff, q);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) q[c] = q[c] + xe[k][c];
-                Spin<S>::store(psi, V, xe_i, q);
+                Spin<S>::store(psi, V, xe_i + qoff, q);
             }
         }
     }
@@ -312,6 +324,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     }
     const R kappa = (R)f->lat.kappa;
     const long half = (long)nbc * Vbh;
+    const bool pair = sizeof(S) == 4 && f->st_sap_pair && use_lds && Vbh == 128 && NT == 128 && nrhs % 2 == 0;
     // Algorithmic work of one sweep per (even, odd) site pair of the swept
     // colour, with h = 165 flop per hop times the hops that stay inside the
     // block (sum over mu of 2 (b_mu - 1) / b_mu per site):
@@ -347,6 +360,15 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
         kern<<<grid, NT, sh, s>>>(eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, g.V, g.Vh, Vbh, nbc, col, \
                                   kappa, nmr, first, gbuf);                                                    \
     }
+            if constexpr (sizeof(S) == 4) {
+                // two right-hand sides per workgroup (4^4 blocks, even count)
+                if (pair) {
+                    k_sap_sweep<S, R, LF, CF, true, 1, 256, 128, 2><<<dim3(nbc, nrhs / 2), 2 * NT, 2 * lds, s>>>(
+                        eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, g.V, g.Vh, Vbh, nbc, col, kappa,
+                        nmr, first, gbuf);
+                    continue;
+                }
+            }
             if (use_lds) {
                 if (Vbh == 128) DFL_SAP_LAUNCH(true, 1, 256, 128)
                 else if (Vbh == 256) DFL_SAP_LAUNCH(true, 1, 256, 256)

@@ -200,6 +200,28 @@ def test_sap_reduced_precision_matches_quantised_oracle(storage):
         assert rel(psi[r], ref[r]) <= SAP_TOL, (r, rel(psi[r], ref[r]))
 
 
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_sap_paired_right_hand_sides(storage):
+    """Schwarz sweeps with two right-hand sides per workgroup (4^4 blocks)
+    and with one: the same per-site arithmetic, block reductions in another
+    order, so both match the quantised oracle and each other to rounding."""
+    torch, dfl = _gpu()
+    c = case(*MID)
+    eta = torch.from_numpy(synth.gaussian_spinor(c.dims, 4, 1006).astype(np.complex64)).cuda()
+    sp = dfl.SapParams(ncy=5, nmr=4, storage=storage)
+    try:
+        c.field.tune(dfl.Field.TUNE_SAP_PAIR, 1)
+        paired = dfl.sap_precond(c.field, eta, sp).cpu().numpy()
+        c.field.tune(dfl.Field.TUNE_SAP_PAIR, 0)
+        single = dfl.sap_precond(c.field, eta, sp).cpu().numpy()
+    finally:
+        c.field.tune(dfl.Field.TUNE_SAP_PAIR, 1)
+    ref = c.qop(storage).sap(eta.cpu().numpy().astype(np.complex128), c.block, 5, 4)
+    for r in range(4):
+        assert rel(paired[r], ref[r]) <= SAP_TOL and rel(single[r], ref[r]) <= SAP_TOL, r
+        assert rel(paired[r], single[r]) <= 1e-5, (r, rel(paired[r], single[r]))
+
+
 @pytest.mark.parametrize("dims,block", [
     ((16, 8, 8, 8), (8, 4, 4, 4)),      # 4^3 x 8 blocks, 256 threads
     ((12, 12, 12, 12), (6, 6, 6, 6)),   # 648 sites per parity: ragged workgroup
