@@ -730,6 +730,16 @@ int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int
     return (poll && !done) ? QCD_NOCONV : 0;
 }
 
+// A[B][dd][k][l] = u9[dd][B][k] for one column l
+__global__ void k_little_column(const double2 *__restrict__ u9, double2 *__restrict__ A, int Nb, int Ns, int l) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9L * Nb * Ns) return;
+    const int k = (int)(i % Ns);
+    const long dB = i / Ns;
+    const int B = (int)(dB % Nb), dd = (int)(dB / Nb);
+    A[(((size_t)B * 9 + dd) * Ns + k) * Ns + l] = u9[i];
+}
+
 // A[:, d, :, l] for every l from the direction-resolved operator
 int build_little(qcd_dfl d, hipStream_t s) {
     qcd_field f = d->f;
@@ -745,8 +755,6 @@ int build_little(qcd_dfl d, hipStream_t s) {
     double2 *out9 = reinterpret_cast<double2 *>(static_cast<char *>(p) + fbytes);
     double2 *u9 = out9 + (size_t)12 * V * 9;
     double2 *work = u9 + (size_t)9 * Nb * Ns;
-    std::vector<double2> hu((size_t)9 * Nb * Ns);
-    std::vector<double2> hA((size_t)Nb * 9 * Ns * Ns);
     for (int l = 0; l < Ns; ++l) {
         {
             ProfScope ps(PROF_DFL, s);
@@ -758,14 +766,9 @@ int build_little(qcd_dfl d, hipStream_t s) {
         DFL_HIP(hipGetLastError());
         // u9[dd][B][k] = (phi_{B,k}, out_dd) ; treat the 9 outputs as 9 right-hand sides
         DFL_TRY(restrict_v<double2>(d, out9, u9, 9, s));
-        DFL_HIP(hipMemcpyAsync(hu.data(), u9, ubytes, hipMemcpyDeviceToHost, s));
-        DFL_HIP(hipStreamSynchronize(s));
-        for (int dd = 0; dd < 9; ++dd)
-            for (int B = 0; B < Nb; ++B)
-                for (int k = 0; k < Ns; ++k)
-                    hA[(((size_t)B * 9 + dd) * Ns + k) * Ns + l] = hu[((size_t)dd * Nb + B) * Ns + k];
+        k_little_column<<<nblocks(9L * Nb * Ns, 256), 256, 0, s>>>(u9, d->A, Nb, Ns, l);
+        DFL_HIP(hipGetLastError());
     }
-    DFL_HIP(hipMemcpyAsync(d->A, hA.data(), sizeof(double2) * hA.size(), hipMemcpyHostToDevice, s));
     DFL_HIP(hipMemsetAsync(f->flag, 0, sizeof(int), s));
     k_block_inverse<<<nblocks(Nb, 64), 64, 0, s>>>(d->A, d->Dinv, work, Nb, Ns, f->flag);
     DFL_HIP(hipGetLastError());
