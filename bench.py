@@ -185,17 +185,34 @@ STENCIL_MODES = {
 }
 
 
-def stencil_sweep(lattices, storages, nrhs_list, reps, log):
+def stencil_sweep(lattices, storages, nrhs_list, reps, log, cpu=True):
     """Dirac-operator GB/s and Gflop/s per storage mode and right-hand-side
-    count (kernel time from HIP events; pack/unpack kernels excluded)."""
+    count (kernel time from HIP events; pack/unpack kernels excluded).  With
+    cpu, the oracle's FP64 operator on the host is timed beside it (one
+    application, one right-hand side, the same algorithmic bytes and flops)."""
     import torch
     import paper_1605_00564_amd as dfl
     rows = []
     for dims in lattices:
         U = synth.gauge_field(dims, 0.4, 1)
         fld = dfl.Field(dims, (4, 4, 4, 4), 0.124, 1.5, torch.from_numpy(U).cuda())
-        del U
         V = synth.volume(dims)
+        if cpu:
+            import oracle
+            op = oracle.Operator(dims, U, 0.124, 1.5, -1)
+            x = synth.gaussian_spinor(dims, 1, 1001)[0]
+            op.M(x)
+            t = time.perf_counter()
+            op.M(x)
+            dt = time.perf_counter() - t
+            by = V * (4 * 144.0 + 576.0 + 2 * 192.0)
+            row = {"lattice": "x".join(map(str, dims)), "storage": "f64", "nrhs": 1, "device": "oracle (host)",
+                   "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "ms": 1e3 * dt,
+                   "GB/s": by / dt / 1e9, "Gflop/s": 1872.0 * V / dt / 1e9}
+            rows.append(row)
+            log(json.dumps(row))
+            del op, x
+        del U
         for mode in storages:
             st, sp = STENCIL_MODES[mode]
             dt = torch.complex128 if st == F64 else torch.complex64
@@ -449,7 +466,7 @@ def main():
     if args.stencil_sweep:
         lats = [tuple(int(v) for v in s.split("x")) for s in args.sweep_lattices.split(",")]
         rows = stencil_sweep(lats, args.sweep_storage.split(","),
-                             [int(v) for v in args.sweep_nrhs.split(",")], 10, log)
+                             [int(v) for v in args.sweep_nrhs.split(",")], 10, log, cpu=not args.no_cpu_baseline)
         print(json.dumps({"stencil_sweep": rows}), flush=True)
         return
     work = WORKLOADS[args.workload]
