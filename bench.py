@@ -194,11 +194,12 @@ def stencil_sweep(lattices, storages, nrhs_list, reps, log, cpu=True):
     import paper_1605_00564_amd as dfl
     rows = []
     for dims in lattices:
-        U = synth.gauge_field(dims, 0.4, 1)
+        U = synth.gauge_field(dims, 0.4, 1, progress=lambda f: log(f"[sweep] {dims}: gauge field {100 * f:.0f}%"))
         fld = dfl.Field(dims, (4, 4, 4, 4), 0.124, 1.5, torch.from_numpy(U).cuda())
         V = synth.volume(dims)
         if cpu:
             import oracle
+            log(f"[sweep] {dims}: oracle operator (clover term and its inverse) on the host")
             op = oracle.Operator(dims, U, 0.124, 1.5, -1)
             x = synth.gaussian_spinor(dims, 1, 1001)[0]
             op.M(x)

@@ -140,7 +140,8 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
                                                     const int *__restrict__ nbr, const short *__restrict__ lnbr,
                                                     const int *__restrict__ border, long V, long Vh, int Vbh,
                                                     R kappa, const void *__restrict__ b = nullptr,
-                                                    double *__restrict__ part = nullptr) {
+                                                    double *__restrict__ part = nullptr,
+                                                    float4 *__restrict__ rho32 = nullptr) {
     using T = typename Chunk<S>::T;
     constexpr int NCH = Spin<S>::NCH;
     constexpr bool HALF = NCH == 3;
@@ -238,6 +239,12 @@ __global__ void __launch_bounds__(MAXT) k_dirac_blk(const void *__restrict__ in,
         }
     }
     Spin<SO>::store(outb, V, xo, o);
+    if constexpr (RES) {
+        // the residual rounded to FP32 as well, for the next Krylov cycle
+        if (rho32 != nullptr)
+            Spin<float>::store(wave_uniform(reinterpret_cast<char *>(rho32) + (size_t)rg * NR * 96 * V), V,
+                               x + (unsigned)(q * 6 * V), o);
+    }
 }
 
 // Link rows 0-1 of a half-precision reconstruct-12 link from three 8-byte
@@ -427,7 +434,7 @@ static int launch_dirac(qcd_field f, const void *in, void *out, int nrhs, hipStr
 }
 
 int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int nrhs, double *norm2,
-                hipStream_t s) {
+                hipStream_t s, float4 *rho32) {
     const Geom &g = f->g;
     const int Vb = 2 * g.Vbh;
     const size_t lds = (size_t)12 * Vb * 16;
@@ -438,8 +445,9 @@ int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int
         DFL_TRY(field_buffer(f, BUF_RES, tb + sizeof(double) * (size_t)nrhs * BLAS_NBLK, &tp));
         double2 *t = static_cast<double2 *>(tp);
         DFL_TRY(dirac_internal(f, x, t, nrhs, QCD_F64, QCD_F64, s));
-        return blas_resid(b, t, r, 12 * g.V, nrhs, reinterpret_cast<double *>(static_cast<char *>(tp) + tb), norm2,
-                          s);
+        DFL_TRY(blas_resid(b, t, r, 12 * g.V, nrhs, reinterpret_cast<double *>(static_cast<char *>(tp) + tb), norm2,
+                           s));
+        return rho32 ? blas_d2f(r, rho32, g.V, nrhs, s) : 0;
     }
     void *pp;
     DFL_TRY(field_buffer(f, BUF_RES, sizeof(double) * (size_t)nrhs * g.Nb, &pp));
@@ -453,7 +461,8 @@ int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int
         const dim3 grid((unsigned)g.Nb, (unsigned)(nrhs / nr));
 #define DFL_RES_LAUNCH(MAXT, NR)                                                                        \
     k_dirac_blk<double, double, double, LNK_F64, CLO_F64, MAXT, NR, true><<<grid, Vb * NR, NR * lds, s>>>( \
-        x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh, f->lat.kappa, b, part)
+        x, r, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, f->lnbr, f->border, g.V, g.Vh, g.Vbh, f->lat.kappa, b, part, \
+        rho32)
         if (nr == 4) DFL_RES_LAUNCH(1024, 4);
         else if (nr == 2) DFL_RES_LAUNCH(512, 2);
         else if (Vb <= 256) DFL_RES_LAUNCH(256, 1);

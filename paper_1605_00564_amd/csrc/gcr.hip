@@ -8,6 +8,7 @@
 // residual rho and the Krylov pairs (z_k, w_k) are stored in FP32 (or FP64
 // when the preconditioner runs in FP64), and every Gram-Schmidt coefficient
 // is accumulated in FP64.
+#include <type_traits>
 #include <cmath>
 
 #include "blas.h"
@@ -113,11 +114,17 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     // the search directions M P_R z = P_L M z only span range(P_L), so the
     // part of r outside it, left by inexact little solves and FP32 rounding,
     // is removed here, in FP64, before the next cycle.
+    // FP32 Krylov vectors: the FP64 residual kernel also writes rho, the
+    // residual rounded to FP32, which the next cycle starts from
+    float4 *rho32 = nullptr;
+    if constexpr (std::is_same_v<E, float4>) rho32 = rho;
+    bool rho_ready = false;
     auto low_mode_correction = [&]() -> int {
         DFL_TRY(dfl_low_mode(p->dfl, x_zero ? b : r, x, n, p->little_tol,
                              ns ? p->little_maxit : std::max(p->little_maxit, 200), x_zero, s));
         x_zero = false;
-        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
+        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s, rho32));
+        rho_ready = rho32 != nullptr;
         if (ns) return 0;
         DFL_TRY(fetch(f, sc.red, n, s, h));
         for (int i = 0; i < n; ++i) rn[i] = std::sqrt(h[i]);
@@ -137,7 +144,8 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
             DFL_TRY(low_mode_correction());
             if (p->fixed_iters <= 0 && converged(rn)) break;
         }
-        DFL_TRY(to_inner(r, rho, V, n, s));
+        if (!rho_ready) DFL_TRY(to_inner(r, rho, V, n, s));
+        rho_ready = false;
         const std::vector<double> rstart = rn;
         int k = 0;
         while (k < nkv && iters < limit) {
@@ -167,7 +175,9 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
         }
         DFL_TRY(gcr_trisolve(sc.R, sc.cvec, n, k, sc.alpha, s));
         DFL_TRY(accum(x, Z, V, n, k, sc.alpha, s));
-        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s));
+        // without deflation the next cycle starts from this residual
+        DFL_TRY(dirac_resid(f, x, b, r, n, sc.red, s, p->dfl ? nullptr : rho32));
+        rho_ready = !p->dfl && rho32 != nullptr;
         if (!ns) {
             DFL_TRY(fetch(f, sc.red, n, s, h));
             for (int i = 0; i < n; ++i) {

@@ -667,9 +667,10 @@ inline CloFmt clo_fmt(qcd_prec p) { return p == QCD_F64 ? CLO_F64 : p == QCD_F32
 // --- internal operations (device pointers in the internal layout) ---------
 // out = M in on internal vectors; nrhs fields of type S (double or float)
 // r = b - M x with the FP64 operator and ||r||^2 per right-hand side into
-// `norm2` (device, n doubles); internal FP64 vectors
+// `norm2` (device, n doubles); internal FP64 vectors.  rho32 (optional):
+// also r rounded to internal FP32 vectors
 int dirac_resid(qcd_field f, const double2 *x, const double2 *b, double2 *r, int nrhs, double *norm2,
-                hipStream_t s);
+                hipStream_t s, float4 *rho32 = nullptr);
 int dirac_internal2(qcd_field f, const void *in, qcd_prec vin, void *out, qcd_prec vout, int nrhs,
                     qcd_prec storage, hipStream_t s);
 int dirac_internal(qcd_field f, const void *in, void *out, int nrhs, qcd_prec vec, qcd_prec storage,
