@@ -1,10 +1,12 @@
 """Parity at the headline size, 32^3 x 64 with 4^4 Schwarz blocks, in the
-launch configuration the benchmark times: 12 right-hand sides per stencil
-and Schwarz launch, FP16 link/clover storage for the sloppy path.
+launch configuration the benchmark times: 24 right-hand sides per stencil
+and Schwarz launch (the stencil then holds each block's links in LDS and
+the Schwarz sweep pairs right-hand sides), FP16 link/clover storage for the
+sloppy path.
 
 The oracle applies M and M_SAP to a whole 32^3 x 64 field in seconds, so
-sampled right-hand sides of a 12-wide batch are compared element by element
-(the batch is two Gaussian spinors times twelve distinct phases; M and M_SAP
+sampled right-hand sides of a 24-wide batch are compared element by element
+(the batch is two Gaussian spinors times 24 distinct phases; M and M_SAP
 are linear, so the oracle results of the two spinors cover every member).
 The solves are checked through a property that holds at any size: the FP64
 residual of sampled solutions, recomputed by the oracle's operator.
@@ -23,7 +25,8 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 DIMS, BLOCK = (64, 32, 32, 32), (4, 4, 4, 4)
 EPS, KAPPA, CSW = 0.4, 0.124, 1.5
 SAP_TOL = 3e-5          # chain of about 30 FP32 applications, as for the small lattices
-PHASES = np.exp(1j * np.arange(12))
+NB = 24                 # right-hand sides per launch, as in the benchmark
+PHASES = np.exp(1j * np.arange(NB))
 
 _st = {}
 
@@ -50,9 +53,9 @@ def state():
 
 
 def batch(dtype):
-    """12 right-hand sides: spinor r % 2 times phase r."""
+    """NB right-hand sides: spinor r % 2 times phase r."""
     s = state()
-    return np.stack([(PHASES[r] * s["base"][r % 2]).astype(dtype) for r in range(12)])
+    return np.stack([(PHASES[r] * s["base"][r % 2]).astype(dtype) for r in range(NB)])
 
 
 def quantised_operator(storage):
@@ -74,7 +77,7 @@ def test_fullsize_dirac_fp64_batch():
     x = batch(np.complex128)
     y = dfl.dirac_apply(s["fld"], torch.from_numpy(x).cuda(), storage=F64).cpu().numpy()
     ref = [s["op"].M(s["base"][k]) for k in range(2)]
-    for r in (0, 5, 11):
+    for r in (0, 5, 23):
         err = rel(y[r], PHASES[r] * ref[r % 2])
         print("fp64 dirac 32^3x64 rhs", r, "rel err", err)
         assert err <= 1e-12
@@ -86,7 +89,7 @@ def test_fullsize_dirac_fp16_storage_batch():
     x = batch(np.complex64)
     y = dfl.dirac_apply(s["fld"], torch.from_numpy(x).cuda(), storage=F16).cpu().numpy()
     q = quantised_operator(F16)
-    for r in (0, 11):
+    for r in (0, 23):
         xr = x[r].astype(np.complex128)
         err = rel(y[r], q.M(xr))
         print("fp16-storage dirac 32^3x64 rhs", r, "rel err", err)
@@ -99,7 +102,7 @@ def test_fullsize_sap_fp16_storage_batch():
     x = batch(np.complex64)
     psi = dfl.sap_precond(s["fld"], torch.from_numpy(x).cuda(), dfl.SapParams(5, 4, F16)).cpu().numpy()
     q = quantised_operator(F16)
-    for r in (0, 11):
+    for r in (0, 23):
         ref = q.sap(x[r].astype(np.complex128), BLOCK, 5, 4)
         err = rel(psi[r], ref)
         print("fp16-storage sap 32^3x64 rhs", r, "rel err", err)
@@ -118,7 +121,8 @@ def test_fullsize_ama_residuals():
     d = dfl.Deflation(s["fld"], Ns=12, ninv=5, seed=7, sap=sloppy_sap)
     sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sloppy_sap, dfl=d, little_tol=1e-6, little_maxit=16)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=exact_sap, dfl=d, little_tol=1e-10, little_maxit=16)
-    xs, xe, infs, infe = dfl.ama_solve(s["fld"], positions, [True, False], sloppy, exact, dtype=torch.complex128)
+    xs, xe, infs, infe = dfl.ama_solve(s["fld"], positions, [True, False], sloppy, exact, dtype=torch.complex128,
+                                       batch=NB)
     assert all(i.status == 0 for i in infs) and all(i.status == 0 for i in infe)
     op = s["op"]
     for g, pos in enumerate(positions):
