@@ -145,6 +145,15 @@ def test_workspace_cache_keeps_and_trims_closed_handles_buffers():
     x2, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=False)
     for r in range(4):
         assert torch.equal(x2[r], x[r])
+    # graphs captured before a trim are dropped: capture, trim, capture again
+    xg1, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)
+    xg2, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)      # replay
+    fld.trim()
+    xg3, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)      # eager run and a new capture
+    xg4, _ = dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)      # its replay
+    for r in range(4):
+        for y in (xg2, xg3, xg4):
+            assert torch.equal(y[r], xg1[r])
     d.close()
     fld.close()
     dfl.workspace_trim(0)
