@@ -82,3 +82,13 @@ def test_autotuner_prior_ranks_block_shapes_per_site():
     cands = [(4, 4, 4, 4), (8, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8)]
     assert tune.rank_by_prior(cands, prior) == [(8, 4, 4, 4), (6, 6, 6, 6), (4, 4, 4, 4), (8, 8, 8, 8)]
     assert tune.rank_by_prior(cands, None) == cands
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
