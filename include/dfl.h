@@ -256,7 +256,9 @@ int make_z2_sources(qcd_field f, unsigned long long seed, long long index0, int 
 int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_prec io, int t_sink, int mu,
                             hipStream_t stream);
 
-/* Launch choices of a handle's Dirac stencil, for the autotuner:
+/* Launch choices of a handle's Dirac stencil and Schwarz sweeps, for the
+ * autotuner (defaults: block-staged, automatic, lexicographic, automatic,
+ * 1, 1):
  * QCD_TUNE_STENCIL_BLOCK  1 = one workgroup per Schwarz block with the
  *                         block's spinors staged in LDS (when it fits),
  *                         0 = site tiles;
