@@ -92,3 +92,10 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_binding_covers_every_declared_function():
+    """The Python binding reaches every function include/dfl.h declares."""
+    src = open(os.path.join(ROOT, "paper_1605_00564_amd", "_lib.py")).read()
+    missing = [n for n in declared_functions() if n not in src]
+    assert not missing, missing
