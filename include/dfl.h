@@ -199,27 +199,69 @@ typedef struct {
 int gcr_solve(qcd_field f, const qcd_gcr *p, const void *b, void *x, int nrhs, qcd_prec io,
               qcd_info *info /* host [nrhs] */, hipStream_t stream);
 
-/* All-mode averaging (section 2.1): for every source position g in G the 12
- * spin-colour point sources eta = delta_{x,x_g} delta_{sc,sc'} are solved
- * with the sloppy parameters; positions flagged in exact[] are also solved
- * with the exact parameters.  Positions must map the block checkerboard
- * onto itself relative to each other (shifts by whole blocks with an even
- * total number of block steps), so that M_SAP is covariant under the
- * translations relating them (section 2.2); otherwise QCD_EGEOM.
- * x_sloppy[g] and x_exact[e] are DEVICE buffers of 12 canonical vectors
- * (sc = 3*spin + colour) at io precision; e counts flagged positions in order.
- * batch: number of right-hand sides solved together (0: library choice). */
+/* All-mode averaging (section 2.1).  The estimator
+ *   O_AMA = (1/N_org) sum_{f in F} [O^f - O^(appx)f] + (1/N_G) sum_{g in G} O^(appx)g
+ * (eqs. caa1, caa2) needs truncated ("sloppy") solutions for every source g
+ * of the set G and exact ones for a subset F of G.  A source is one of:
+ *   QCD_SRC_POINT  the 12 spin-colour point sources delta_{x,pos}
+ *                  delta_{sc,sc'} (12 right-hand sides, sc = 3*spin+colour);
+ *                  positions of one set must be related by translations of
+ *                  whole blocks with an even total number of block steps, so
+ *                  that M_SAP is covariant under them (section 2.2), else
+ *                  QCD_EGEOM;
+ *   QCD_SRC_Z2     nvec Z2-noise vectors, numbers index .. index+nvec-1 of
+ *                  the stream `seed` (the vectors of make_z2_sources);
+ *   QCD_SRC_SEQ    the 12 sequential sources (section 2.3) of 12 forward
+ *                  solutions vec (DEVICE, canonical, io precision):
+ *                  gamma_5 gamma_mu gamma_5 psi on timeslice t_sink, zero
+ *                  elsewhere (as make_sequential_sources);
+ *   QCD_SRC_VEC    nvec caller vectors vec (DEVICE, canonical, io precision).
+ * Outputs: x_sloppy[i] receives the solutions of source i (all its vectors
+ * in order, canonical, sloppy_out precision); x_exact[e] those of the e-th
+ * source flagged in exact[] (io precision).  info_sloppy / info_exact (host,
+ * may be NULL) get one entry per right-hand side in the same order.
+ * Sloppy parameters with fixed_iters > 0 (the truncated solves of section
+ * 3.5, Table 3) run without host synchronisation, each batch size replayed
+ * from one captured HIP graph; a solution the fixed count leaves above
+ * sloppy.res is solved again with the residual-stopping solver (its info
+ * then counts both solves' iterations).  Other solves stop at their res.
+ * Source vectors and outputs must not overlap.  Returns QCD_NOCONV when a
+ * solution misses its target; errors as for gcr_solve. */
+typedef enum { QCD_SRC_POINT = 0, QCD_SRC_Z2 = 1, QCD_SRC_SEQ = 2, QCD_SRC_VEC = 3 } qcd_src_kind;
+
 typedef struct {
-    int npos;
-    const int *pos;                /* host [npos][4] = (t, x, y, z) */
-    const unsigned char *exact;    /* host [npos], nonzero = also solve exactly */
+    int kind;                  /* qcd_src_kind */
+    int pos[4];                /* POINT: (t, x, y, z) */
+    unsigned long long seed;   /* Z2: noise stream */
+    long long index;           /* Z2: first noise vector */
+    int nvec;                  /* Z2, VEC: number of vectors (POINT, SEQ: 12) */
+    int t_sink, mu;            /* SEQ: insertion timeslice and direction */
+    const void *vec;           /* SEQ: 12 forward solutions; VEC: nvec sources */
+} qcd_source;
+
+typedef struct {
+    int nsrc;
+    const qcd_source *src;         /* host [nsrc] */
+    const unsigned char *exact;    /* host [nsrc] or NULL: nonzero = also solve exactly */
     qcd_gcr sloppy, exact_params;
-    int batch;
+    qcd_prec sloppy_out;           /* QCD_F64 or QCD_F32 */
+    int batch;                     /* right-hand sides per solver launch (0: library choice) */
 } qcd_ama;
 
 int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const *x_exact, qcd_prec io,
-              qcd_info *info_sloppy /* host [npos*12] */, qcd_info *info_exact /* host [nexact*12] */,
-              hipStream_t stream);
+              qcd_info *info_sloppy, qcd_info *info_exact, hipStream_t stream);
+
+/* The AMA sets of several gauge fields (the orbit G over an ensemble,
+ * section 2.1) in one call: sets[k], x_sloppy[k], x_exact[k],
+ * info_sloppy[k], info_exact[k] belong to fields[k], with the meaning of
+ * ama_solve.  Every field's handle keeps its own block shape, deflation
+ * subspace, launch choices and captured graphs (an autotuner sets them per
+ * field beforehand).  All sets are validated before the first launch; the
+ * fields are then solved in order on `stream`.  All handles must live on
+ * the current device. */
+int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, void *const *const *x_sloppy,
+                    void *const *const *x_exact, qcd_prec io, qcd_info *const *info_sloppy,
+                    qcd_info *const *info_exact, hipStream_t stream);
 
 /* The solve of gcr_solve for nrhs right-hand sides given one by one
  * (b[r], x[r]: caller-owned device pointers to canonical [V][4][3] vectors

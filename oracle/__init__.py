@@ -501,24 +501,6 @@ def ama_positions(dims, block, x0, steps):
     return out
 
 
-def ama_solve(op: Operator, sites, exact_mask, sloppy: dict, exact: dict):
-    """Sloppy propagators for every position and exact ones for the subset
-    (the two inputs of the AMA estimator, eqs. caa1-caa2).  Each position
-    gets 12 point sources (spin-colour sc = 3*spin + colour)."""
-    xs, xe, infos, infoe = [], [], [], []
-    for site, ex in zip(sites, exact_mask):
-        for sc in range(12):
-            eta = synth.point_source(op.dims, site, sc)
-            x, inf = solve(op, eta, **sloppy)
-            xs.append(x)
-            infos.append(inf)
-            if ex:
-                x, inf = solve(op, eta, **exact)
-                xe.append(x)
-                infoe.append(inf)
-    return xs, xe, infos, infoe
-
-
 def ama_estimate(O_exact, O_appx_f, O_appx_g):
     """O_AMA = (1/N_org) sum_f [O^f - O^(appx) f] + (1/N_G) sum_g O^(appx) g (eqs. caa1-caa2)."""
     rest = np.mean(np.asarray(O_exact) - np.asarray(O_appx_f), axis=0)

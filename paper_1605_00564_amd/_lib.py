@@ -14,6 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
+SRC_POINT, SRC_Z2, SRC_SEQ, SRC_VEC = 0, 1, 2, 3
 NOCONV = 1
 PROF_CLASSES = ("dirac", "sap", "deflation", "little", "blas", "other")
 
@@ -53,9 +54,14 @@ class _Info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("rel_res", C.c_double)]
 
 
+class _Source(C.Structure):
+    _fields_ = [("kind", C.c_int), ("pos", C.c_int * 4), ("seed", C.c_ulonglong), ("index", C.c_longlong),
+                ("nvec", C.c_int), ("t_sink", C.c_int), ("mu", C.c_int), ("vec", C.c_void_p)]
+
+
 class _Ama(C.Structure):
-    _fields_ = [("npos", C.c_int), ("pos", C.POINTER(C.c_int)), ("exact", C.POINTER(C.c_ubyte)),
-                ("sloppy", _Gcr), ("exact_params", _Gcr), ("batch", C.c_int)]
+    _fields_ = [("nsrc", C.c_int), ("src", C.POINTER(_Source)), ("exact", C.POINTER(C.c_ubyte)),
+                ("sloppy", _Gcr), ("exact_params", _Gcr), ("sloppy_out", C.c_int), ("batch", C.c_int)]
 
 
 _lib = None
@@ -100,6 +106,8 @@ def load():
         ("deflation_prolong", [P, P, P, I, I, P]),
         ("gcr_solve", [P, C.POINTER(_Gcr), P, P, I, I, C.POINTER(_Info), P]),
         ("ama_solve", [P, C.POINTER(_Ama), C.POINTER(P), C.POINTER(P), I, C.POINTER(_Info), C.POINTER(_Info), P]),
+        ("ama_solve_multi", [I, C.POINTER(P), C.POINTER(_Ama), C.POINTER(C.POINTER(P)), C.POINTER(C.POINTER(P)), I,
+                             C.POINTER(C.POINTER(_Info)), C.POINTER(C.POINTER(_Info)), P]),
         ("qcd_workspace_cached", [I, C.POINTER(C.c_size_t)]),
         ("qcd_workspace_trim", [I]),
         ("qcd_field_trim", [P]),
@@ -404,34 +412,124 @@ def gcr_solve_batched(field: Field, b_list, params: GcrParams, x_list=None, batc
     return x_list, [SolveInfo(i.status, i.iters, i.rel_res) for i in info]
 
 
-def ama_solve(field: Field, positions, exact_flags, sloppy: GcrParams, exact: GcrParams, dtype=None, batch=0,
-              out_sloppy=None, out_exact=None):
-    """Sloppy solves of the 12 point sources at every position, exact solves
-    at the flagged ones.  Returns (x_sloppy[npos], x_exact[nexact], info_s, info_e).
-    Output tensors ([12, V, 4, 3] each) may be passed in to avoid allocation."""
+@dataclass
+class Source:
+    """One source of an AMA set (see ama_solve in include/dfl.h)."""
+    kind: int = SRC_POINT
+    pos: tuple = (0, 0, 0, 0)
+    seed: int = 0
+    index: int = 0
+    nvec: int = 0
+    t_sink: int = 0
+    mu: int = 3
+    vec: object = None     # SEQ: forward solutions [12, V, 4, 3]; VEC: sources [nvec, V, 4, 3]
+
+    @property
+    def count(self):
+        return 12 if self.kind in (SRC_POINT, SRC_SEQ) else self.nvec
+
+    def c(self):
+        return _Source(self.kind, (C.c_int * 4)(*[int(v) for v in self.pos]), int(self.seed), int(self.index),
+                       int(self.nvec), int(self.t_sink), int(self.mu),
+                       self.vec.data_ptr() if self.vec is not None else None)
+
+
+def point(pos) -> Source:
+    return Source(SRC_POINT, tuple(pos))
+
+
+def z2(seed: int, index: int = 0, nvec: int = 1) -> Source:
+    return Source(SRC_Z2, seed=seed, index=index, nvec=nvec)
+
+
+def sequential(fwd, t_sink: int, mu: int = 3) -> Source:
+    return Source(SRC_SEQ, t_sink=t_sink, mu=mu, vec=fwd)
+
+
+def vectors(v) -> Source:
+    return Source(SRC_VEC, nvec=int(v.shape[0]), vec=v)
+
+
+def _ama_struct(field, sources, exact_flags, sloppy, exact, dtype, sloppy_dtype, batch, out_sloppy, out_exact):
+    torch = _torch()
+    srcs = [s if isinstance(s, Source) else point(s) for s in sources]
+    n = len(srcs)
+    for s in srcs:
+        if s.vec is not None:
+            if s.vec.dtype != dtype or not s.vec.is_contiguous() or s.vec.numel() != s.count * field.V * 12:
+                raise ValueError("source vectors must be contiguous [n, V, 4, 3] of the io dtype")
+    flags = [bool(e) for e in exact_flags] if exact_flags is not None else [False] * n
+    xs = out_sloppy if out_sloppy is not None else [
+        torch.empty((s.count, field.V, 4, 3), dtype=sloppy_dtype, device="cuda") for s in srcs]
+    xe = out_exact if out_exact is not None else [
+        torch.empty((s.count, field.V, 4, 3), dtype=dtype, device="cuda") for s, e in zip(srcs, flags) if e]
+    ex_srcs = [s for s, e in zip(srcs, flags) if e]
+    for t, s in zip(xs, srcs):
+        if t.dtype != sloppy_dtype or not t.is_contiguous() or t.numel() != s.count * field.V * 12:
+            raise ValueError("sloppy outputs must be contiguous [n, V, 4, 3] of the sloppy dtype")
+    for t, s in zip(xe, ex_srcs):
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != s.count * field.V * 12:
+            raise ValueError("exact outputs must be contiguous [n, V, 4, 3] of the io dtype")
+    if len(xs) != n or len(xe) != len(ex_srcs):
+        raise ValueError("one output tensor per source (sloppy) and per flagged source (exact)")
+    keep = dict(src=(_Source * n)(*[s.c() for s in srcs]), ex=(C.c_ubyte * n)(*[1 if e else 0 for e in flags]),
+                ps=(C.c_void_p * max(n, 1))(*[t.data_ptr() for t in xs]),
+                pe=(C.c_void_p * max(len(xe), 1))(*[t.data_ptr() for t in xe]))
+    ns = sum(s.count for s in srcs)
+    ne = sum(s.count for s in ex_srcs)
+    keep["info_s"] = (_Info * max(ns, 1))()
+    keep["info_e"] = (_Info * max(ne, 1))()
+    a = _Ama(n, C.cast(keep["src"], C.POINTER(_Source)), C.cast(keep["ex"], C.POINTER(C.c_ubyte)), sloppy.c(),
+             exact.c(), F64 if sloppy_dtype == torch.complex128 else F32, batch)
+    return a, keep, xs, xe, ns, ne
+
+
+def _infos(arr, n):
+    return [SolveInfo(i.status, i.iters, i.rel_res) for i in arr[:n]]
+
+
+def ama_solve(field: Field, sources, exact_flags, sloppy: GcrParams, exact: GcrParams, dtype=None, batch=0,
+              out_sloppy=None, out_exact=None, sloppy_dtype=None):
+    """Sloppy solves of every source, exact solves of the flagged ones.
+    sources: Source objects (point, z2, sequential, vectors) or (t, x, y, z)
+    positions (point sources).  dtype: io precision (exact outputs, source
+    vectors); sloppy_dtype: precision of the sloppy outputs (default dtype).
+    Returns (x_sloppy[nsrc], x_exact[nexact], info_s, info_e); outputs are
+    [count, V, 4, 3] per source and may be passed in to avoid allocation."""
     torch = _torch()
     dtype = dtype or torch.complex64
-    npos = len(positions)
-    pos = (C.c_int * (4 * npos))(*[int(v) for p in positions for v in p])
-    ex = (C.c_ubyte * npos)(*[1 if e else 0 for e in exact_flags])
-    nex = sum(1 for e in exact_flags if e)
-    xs = out_sloppy if out_sloppy is not None else [
-        torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(npos)]
-    xe = out_exact if out_exact is not None else [
-        torch.empty((12, field.V, 4, 3), dtype=dtype, device="cuda") for _ in range(nex)]
-    for t in list(xs) + list(xe):
-        if t.dtype != dtype or not t.is_contiguous() or t.numel() != 12 * field.V * 12:
-            raise ValueError("output tensors must be contiguous [12, V, 4, 3] of the io dtype")
-    ps = (C.c_void_p * max(npos, 1))(*[t.data_ptr() for t in xs])
-    pe = (C.c_void_p * max(nex, 1))(*[t.data_ptr() for t in xe])
-    a = _Ama(npos, C.cast(pos, C.POINTER(C.c_int)), C.cast(ex, C.POINTER(C.c_ubyte)), sloppy.c(), exact.c(), batch)
-    info_s = (_Info * (12 * max(npos, 1)))()
-    info_e = (_Info * (12 * max(nex, 1)))()
+    sloppy_dtype = sloppy_dtype or dtype
+    a, keep, xs, xe, ns, ne = _ama_struct(field, sources, exact_flags, sloppy, exact, dtype, sloppy_dtype, batch,
+                                          out_sloppy, out_exact)
     io = F64 if dtype == torch.complex128 else F32
-    rc = load().ama_solve(field.handle, C.byref(a), ps, pe, io, info_s, info_e, _stream())
+    rc = load().ama_solve(field.handle, C.byref(a), keep["ps"], keep["pe"], io, keep["info_s"], keep["info_e"],
+                          _stream())
     _check(rc, "ama_solve", ok_noconv=True)
-    conv = lambda arr, n: [SolveInfo(i.status, i.iters, i.rel_res) for i in arr[:n]]
-    return xs, xe, conv(info_s, 12 * npos), conv(info_e, 12 * nex)
+    return xs, xe, _infos(keep["info_s"], ns), _infos(keep["info_e"], ne)
+
+
+def ama_solve_multi(fields, sets, dtype=None, sloppy_dtype=None):
+    """The AMA sets of several gauge fields in one library call.  sets[k] is
+    a dict with keys sources, exact_flags, sloppy, exact and optionally
+    batch, out_sloppy, out_exact.  Returns one (x_sloppy, x_exact, info_s,
+    info_e) tuple per field."""
+    torch = _torch()
+    dtype = dtype or torch.complex64
+    sloppy_dtype = sloppy_dtype or dtype
+    nf = len(fields)
+    built = [_ama_struct(f, st["sources"], st.get("exact_flags"), st["sloppy"], st["exact"], dtype, sloppy_dtype,
+                         st.get("batch", 0), st.get("out_sloppy"), st.get("out_exact"))
+             for f, st in zip(fields, sets)]
+    fh = (C.c_void_p * nf)(*[f.handle.value for f in fields])
+    amas = (_Ama * nf)(*[b[0] for b in built])
+    ps = (C.POINTER(C.c_void_p) * nf)(*[C.cast(b[1]["ps"], C.POINTER(C.c_void_p)) for b in built])
+    pe = (C.POINTER(C.c_void_p) * nf)(*[C.cast(b[1]["pe"], C.POINTER(C.c_void_p)) for b in built])
+    iS = (C.POINTER(_Info) * nf)(*[C.cast(b[1]["info_s"], C.POINTER(_Info)) for b in built])
+    iE = (C.POINTER(_Info) * nf)(*[C.cast(b[1]["info_e"], C.POINTER(_Info)) for b in built])
+    io = F64 if dtype == torch.complex128 else F32
+    rc = load().ama_solve_multi(nf, fh, amas, ps, pe, io, iS, iE, _stream())
+    _check(rc, "ama_solve_multi", ok_noconv=True)
+    return [(b[2], b[3], _infos(b[1]["info_s"], b[4]), _infos(b[1]["info_e"], b[5])) for b in built]
 
 
 def workspace_cached(device: int = 0) -> int:

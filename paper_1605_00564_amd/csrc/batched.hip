@@ -18,10 +18,16 @@
 
 namespace dfl {
 
+// A graph is valid for the batch size, the solver parameters, the workspace
+// generation and the two workspace vectors it reads and writes: the
+// solution vectors follow the batch's sources, so their address depends on
+// the batch size of the call that laid out the workspace.
 struct GraphEntry {
     int n;
     qcd_gcr p;
     unsigned gen;
+    const double2 *b64;
+    const double2 *x64;
     hipGraphExec_t exec;
 };
 struct GraphCache {
@@ -38,7 +44,7 @@ void graph_cache_free(qcd_field f) {
 
 namespace {
 
-GraphEntry *find_graph(qcd_field f, int n, const qcd_gcr &p) {
+GraphEntry *find_graph(qcd_field f, int n, const qcd_gcr &p, const double2 *b64, const double2 *x64) {
     auto *c = static_cast<GraphCache *>(f->graphs);
     if (!c) return nullptr;
     // graphs captured before a workspace buffer moved are stale
@@ -50,7 +56,7 @@ GraphEntry *find_graph(qcd_field f, int n, const qcd_gcr &p) {
             ++i;
         }
     for (auto &g : c->e)
-        if (g.n == n && std::memcmp(&g.p, &p, sizeof(qcd_gcr)) == 0) return &g;
+        if (g.n == n && g.b64 == b64 && g.x64 == x64 && std::memcmp(&g.p, &p, sizeof(qcd_gcr)) == 0) return &g;
     return nullptr;
 }
 
@@ -77,7 +83,7 @@ int capture(qcd_field f, const qcd_gcr &p, const double2 *b64, double2 *x64, int
     if (ei != hipSuccess) return set_error(QCD_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
     auto *c = static_cast<GraphCache *>(f->graphs);
     if (!c) f->graphs = c = new GraphCache();
-    c->e.push_back({n, p, f->graph_gen, exec});
+    c->e.push_back({n, p, f->graph_gen, b64, x64, exec});
     return 0;
 }
 
@@ -102,6 +108,30 @@ int read_info(qcd_field f, const qcd_gcr &p, int n, qcd_info *info, hipStream_t 
 }
 
 }  // namespace
+
+int solve_batch(qcd_field f, const qcd_gcr &p, const double2 *b64, double2 *x64, int n, bool graph, qcd_info *info,
+                hipStream_t s, int &status) {
+    if (!graph) {
+        const int rc = gcr_internal(f, &p, b64, x64, n, info, s);
+        if (rc < 0) return rc;
+        if (rc == QCD_NOCONV) status = QCD_NOCONV;
+        return 0;
+    }
+    if (p.fixed_iters <= 0) return set_error(QCD_EINVAL, "graph replay needs fixed_iters > 0");
+    if (GraphEntry *g = find_graph(f, n, p, b64, x64)) {
+        DFL_HIP(hipGraphLaunch(g->exec, s));
+    } else {
+        // eager run without synchronisation (this batch's result, and every
+        // workspace allocated), then capture the same sequence
+        set_nosync(true);
+        const int rc = gcr_internal(f, &p, b64, x64, n, nullptr, s);
+        set_nosync(false);
+        if (rc < 0) return rc;
+        DFL_TRY(capture(f, p, b64, x64, n));
+    }
+    return read_info(f, p, n, info, s, status);
+}
+
 }  // namespace dfl
 
 using namespace dfl;
@@ -122,24 +152,7 @@ extern "C" int gcr_solve_batched(qcd_field f, const qcd_gcr *p, const void *cons
         const int n = std::min(nb, nrhs - r0);
         for (int r = 0; r < n; ++r)
             DFL_TRY(pack_spinor(f, b[r0 + r], io, b64 + (size_t)r * 12 * V, QCD_F64, 1, s));
-        if (graph) {
-            if (GraphEntry *g = find_graph(f, n, *p)) {
-                DFL_HIP(hipGraphLaunch(g->exec, s));
-            } else {
-                // eager run without synchronisation (this batch's result, and
-                // every workspace allocated), then capture the same sequence
-                set_nosync(true);
-                const int rc = gcr_internal(f, p, b64, x64, n, nullptr, s);
-                set_nosync(false);
-                if (rc < 0) return rc;
-                DFL_TRY(capture(f, *p, b64, x64, n));
-            }
-            DFL_TRY(read_info(f, *p, n, info ? info + r0 : nullptr, s, status));
-        } else {
-            const int rc = gcr_internal(f, p, b64, x64, n, info ? info + r0 : nullptr, s);
-            if (rc < 0) return rc;
-            if (rc == QCD_NOCONV) status = QCD_NOCONV;
-        }
+        DFL_TRY(solve_batch(f, *p, b64, x64, n, graph != 0, info ? info + r0 : nullptr, s, status));
         for (int r = 0; r < n; ++r)
             DFL_TRY(unpack_spinor(f, x64 + (size_t)r * 12 * V, QCD_F64, x[r0 + r], io, 1, s));
     }

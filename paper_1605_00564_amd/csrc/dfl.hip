@@ -659,6 +659,8 @@ int little_jacobi_dev(qcd_dfl d, const double2 *v, double2 *z, int n, hipStream_
 // one cycle of min(maxit, nkv) iterations without host synchronisation.
 int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int maxit, bool poll, int *iters_out,
                  double *relres_out, hipStream_t s) {
+    // polled norms pass through the handle's pinned buffer of 4096 doubles
+    if (n > 4096) return set_error(QCD_EINVAL, "too many right-hand sides in one little solve (max 4096)");
     const long N = (long)d->Nb * d->Ns;
     const int nkv = std::max(1, std::min(maxit, 24));
     const size_t vb = sizeof(double2) * N * n;
@@ -985,6 +987,7 @@ int little_dirac_apply(qcd_dfl d, const void *v, void *w, int nrhs, hipStream_t 
 int little_dirac_solve(qcd_dfl d, const void *v, void *w, int nrhs, double tol, int maxit, int *iters,
                        hipStream_t s) {
     if (!d || !v || !w || nrhs <= 0 || maxit < 1) return set_error(QCD_EINVAL, "bad arguments to little_dirac_solve");
+    if (nrhs > 4096) return set_error(QCD_EINVAL, "little_dirac_solve: at most 4096 right-hand sides per call");
     double rel = 0;
     int rc = little_solve(d, static_cast<const double2 *>(v), static_cast<double2 *>(w), nrhs, tol, maxit, true, iters,
                           &rel, s);

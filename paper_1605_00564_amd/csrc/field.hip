@@ -223,6 +223,14 @@ static int make_geom(const qcd_lattice *lat, Geom &g) {
     }
     if (g.V >= (1L << 31) / 12)
         return set_error(QCD_EINVAL, "lattice too large for 32-bit site tables");
+    // Kernels address a table through a buffer descriptor with a 32-bit
+    // chunk offset and a 32-bit element offset.  The largest sum is reached
+    // by two FP64 (or four FP32) right-hand sides of one workgroup: 384 bytes
+    // per site (the FP64 clover table needs 288).
+    if ((unsigned long long)g.V * MAX_OFFSET_BYTES_PER_SITE >= (1ULL << 32))
+        return set_error(QCD_EINVAL, "lattice too large: " + std::to_string(g.V) +
+                                         " sites exceed the 32-bit buffer offsets (at most " +
+                                         std::to_string(((1ULL << 32) - 1) / MAX_OFFSET_BYTES_PER_SITE) + ")");
     g.Vh = g.V / 2;
     g.Vbh = g.Vb / 2;
     return 0;
@@ -648,12 +656,17 @@ int qcd_prof_get(int cls, double *ms, long long *n) {
 }
 
 // Build a field handle from complex128 links already in device memory.
-static int field_create_common(const qcd_lattice *lat, const double2 *canon, hipStream_t s, qcd_field *out) {
+// Parameters and geometry, checked before any device call.
+static int check_lattice(const qcd_lattice *lat, Geom &g) {
     if (lat->bc_t != 1 && lat->bc_t != -1) return set_error(QCD_EINVAL, "bc_t must be +1 or -1");
     if (!(lat->kappa > 0) || !std::isfinite(lat->kappa) || !std::isfinite(lat->csw))
         return set_error(QCD_EINVAL, "kappa must be positive and finite, csw finite");
+    return make_geom(lat, g);
+}
+
+static int field_create_common(const qcd_lattice *lat, const double2 *canon, hipStream_t s, qcd_field *out) {
     Geom g;
-    DFL_TRY(make_geom(lat, g));
+    DFL_TRY(check_lattice(lat, g));
     qcd_field f = new qcd_field_s();
     f->lat = *lat;
     f->g = g;
@@ -765,9 +778,9 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
 int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream_t s, qcd_field *out) {
     if (!lat || !links_host || !out) return set_error(QCD_EINVAL, "null argument to qcd_field_create");
     *out = nullptr;
-    long V = 1;
-    for (int m = 0; m < 4; ++m) V *= lat->dims[m] > 0 ? lat->dims[m] : 0;
-    if (V <= 0) return set_error(QCD_EINVAL, "lattice extents must be positive");
+    Geom g;
+    DFL_TRY(check_lattice(lat, g));
+    const long V = g.V;
     double2 *canon = nullptr;
     int dev = 0;
     DFL_HIP(hipGetDevice(&dev));
@@ -785,6 +798,8 @@ int qcd_field_create(const qcd_lattice *lat, const double *links_host, hipStream
 int qcd_field_create_device(const qcd_lattice *lat, const double *links_dev, hipStream_t s, qcd_field *out) {
     if (!lat || !links_dev || !out) return set_error(QCD_EINVAL, "null argument to qcd_field_create_device");
     *out = nullptr;
+    Geom g;
+    DFL_TRY(check_lattice(lat, g));
     return field_create_common(lat, reinterpret_cast<const double2 *>(links_dev), s, out);
 }
 

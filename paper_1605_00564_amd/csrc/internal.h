@@ -582,6 +582,11 @@ __device__ inline R nb_sign(int e) { return e < 0 ? R(-1) : R(1); }
 // ---------------------------------------------------------------------------
 // geometry and the field handle
 // ---------------------------------------------------------------------------
+// Largest byte offset per lattice site that one buffer access adds to a
+// table base (chunk offset + element offset); make_geom rejects lattices
+// for which it reaches 2^32.
+constexpr unsigned long long MAX_OFFSET_BYTES_PER_SITE = 384;
+
 struct Geom {
     int L[4], b[4], nb[4];
     long V, Vh;
@@ -680,11 +685,25 @@ int sap_internal(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, in
 // GCR on FP64 internal vectors b -> x (info: host array of n, may be null)
 int gcr_internal(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, qcd_info *info,
                  hipStream_t s);
+// n right-hand sides b64 -> x64 (internal FP64), eagerly with the
+// residual-stopping solver (graph = false) or, for a fixed iteration count,
+// replayed from a HIP graph captured on the first call with this batch size,
+// parameters and workspace vectors; status becomes QCD_NOCONV if any
+// solution misses p.res
+int solve_batch(qcd_field f, const qcd_gcr &p, const double2 *b64, double2 *x64, int n, bool graph, qcd_info *info,
+                hipStream_t s, int &status);
 // canonical <-> internal conversion; canon is complex128 (F64) or complex64 (F32)
 int pack_spinor(qcd_field f, const void *canon, qcd_prec io, void *internal, qcd_prec vec, int nrhs,
                 hipStream_t s);
 int unpack_spinor(qcd_field f, const void *internal, qcd_prec vec, void *canon, qcd_prec io, int nrhs,
                   hipStream_t s);
+
+// one source vector built in the internal FP64 layout: Z2 noise vector
+// `index` of the stream `seed`; the sequential source of one canonical
+// forward solution (io precision) on timeslice t_sink with the
+// gamma_5 gamma_mu gamma_5 insertion
+int z2_source_internal(qcd_field f, unsigned long long seed, long long index, double2 *b, hipStream_t s);
+int seq_source_internal(qcd_field f, const void *fwd, qcd_prec io, int t_sink, int mu, double2 *b, hipStream_t s);
 
 // launch geometry helper: grid of g workgroups over n items
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }

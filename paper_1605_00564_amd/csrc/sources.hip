@@ -85,6 +85,62 @@ static Spin4 g5_gmu_g5(int mu) {
     return G;
 }
 
+// The same sources written straight into one internal FP64 right-hand side
+// (the solver's layout), for the AMA driver.
+__global__ void k_z2_internal(double2 *__restrict__ b, unsigned long long key, const int *__restrict__ lex_of,
+                              long V, long index) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= V) return;
+    const unsigned long long base = ((unsigned long long)index * V + lex_of[idx]) * 12;
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc)
+        b[(size_t)sc * V + idx] = make_double2((sm64(key, base + sc) >> 63) ? -1.0 : 1.0, 0.0);
+}
+
+template <class CT>
+__global__ void k_seq_internal(const CT *__restrict__ in, double2 *__restrict__ b, const int *__restrict__ lex_of,
+                               long V, long spatial, int t_sink, Spin4 G) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= V) return;
+    const long lex = lex_of[idx];
+    const bool on = lex / spatial == t_sink;
+    const CT *v = in + (size_t)lex * 12;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double ar = 0, ai = 0;
+            if (on)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double vr = v[3 * t + c].x, vi = v[3 * t + c].y;
+                    ar += G.re[4 * s + t] * vr - G.im[4 * s + t] * vi;
+                    ai += G.re[4 * s + t] * vi + G.im[4 * s + t] * vr;
+                }
+            b[(size_t)(3 * s + c) * V + idx] = make_double2(ar, ai);
+        }
+}
+
+int z2_source_internal(qcd_field f, unsigned long long seed, long long index, double2 *b, hipStream_t s) {
+    const long V = f->g.V;
+    k_z2_internal<<<nblocks(V, 256), 256, 0, s>>>(b, sm64(seed, 6ULL), f->lex_of, V, (long)index);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+int seq_source_internal(qcd_field f, const void *fwd, qcd_prec io, int t_sink, int mu, double2 *b, hipStream_t s) {
+    const long V = f->g.V, spatial = V / f->g.L[0];
+    const Spin4 G = g5_gmu_g5(mu);
+    if (io == QCD_F64)
+        k_seq_internal<double2><<<nblocks(V, 256), 256, 0, s>>>(static_cast<const double2 *>(fwd), b, f->lex_of, V,
+                                                                spatial, t_sink, G);
+    else
+        k_seq_internal<float2><<<nblocks(V, 256), 256, 0, s>>>(static_cast<const float2 *>(fwd), b, f->lex_of, V,
+                                                               spatial, t_sink, G);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
 }  // namespace dfl
 
 using namespace dfl;

@@ -99,3 +99,36 @@ def test_binding_covers_every_declared_function():
     src = open(os.path.join(ROOT, "paper_1605_00564_amd", "_lib.py")).read()
     missing = [n for n in declared_functions() if n not in src]
     assert not missing, missing
+
+
+class _Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("kappa", ctypes.c_double),
+                ("csw", ctypes.c_double), ("bc_t", ctypes.c_int)]
+
+
+def _create(lib, dims, block, kappa=0.124, bc_t=-1):
+    lat = _Lattice((ctypes.c_int * 4)(*dims), (ctypes.c_int * 4)(*block), kappa, 1.5, bc_t)
+    dummy = (ctypes.c_double * 8)()          # never read: the checks come first
+    h = ctypes.c_void_p()
+    lib.qcd_field_create.argtypes = [ctypes.POINTER(_Lattice), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    rc = lib.qcd_field_create(ctypes.byref(lat), ctypes.cast(dummy, ctypes.c_void_p), None, ctypes.byref(h))
+    lib.qcd_last_error.restype = ctypes.c_char_p
+    return rc, lib.qcd_last_error().decode(), h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_lattice_checks_come_before_any_device_call():
+    """Geometry and parameter errors are reported without a device: an odd
+    block, an odd number of blocks, a bad boundary flag, and lattices whose
+    largest buffer offset (384 bytes per site) reaches 2^32.  48^3 x 96 is
+    the largest lattice of the workloads and stays inside the limit."""
+    lib = ctypes.CDLL(LIB)
+    assert _create(lib, (8, 8, 8, 8), (3, 4, 4, 4))[0] == -2
+    assert _create(lib, (12, 8, 8, 8), (4, 4, 4, 4))[0] == -2
+    assert _create(lib, (8, 8, 8, 8), (4, 4, 4, 4), bc_t=0)[0] == -1
+    rc, msg, h = _create(lib, (64, 64, 64, 64), (4, 4, 4, 4))
+    assert rc == -1 and "32-bit buffer offsets" in msg and h is None
+    rc, msg, _ = _create(lib, (112, 56, 56, 56), (4, 4, 4, 4))
+    assert rc == -1 and "32-bit buffer offsets" in msg
+    assert 96 * 48 ** 3 * 384 < 2 ** 32 <= 112 * 56 ** 3 * 384

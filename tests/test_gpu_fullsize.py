@@ -5,11 +5,12 @@ the Schwarz sweep pairs right-hand sides), FP16 link/clover storage for the
 sloppy path.
 
 The oracle applies M and M_SAP to a whole 32^3 x 64 field in seconds, so
-sampled right-hand sides of a 24-wide batch are compared element by element
+every right-hand side of a 24-wide batch is compared element by element
 (the batch is two Gaussian spinors times 24 distinct phases; M and M_SAP
 are linear, so the oracle results of the two spinors cover every member).
-The solves are checked through a property that holds at any size: the FP64
-residual of sampled solutions, recomputed by the oracle's operator.
+The solves, run with the benchmark's parameters, are checked through a
+property that holds at any size: the FP64 residual of every spin-colour
+solution of a position, recomputed by the oracle's operator.
 """
 
 import numpy as np
@@ -24,7 +25,7 @@ pytestmark = pytest.mark.gpu
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DIMS, BLOCK = (64, 32, 32, 32), (4, 4, 4, 4)
 EPS, KAPPA, CSW = 0.4, 0.124, 1.5
-SAP_TOL = 3e-5          # chain of about 30 FP32 applications, as for the small lattices
+SAP_TOL_F16 = 1e-5      # FP16 storage: the per-application floor (see test_gpu_ops)
 NB = 24                 # right-hand sides per launch, as in the benchmark
 PHASES = np.exp(1j * np.arange(NB))
 
@@ -77,41 +78,53 @@ def test_fullsize_dirac_fp64_batch():
     x = batch(np.complex128)
     y = dfl.dirac_apply(s["fld"], torch.from_numpy(x).cuda(), storage=F64).cpu().numpy()
     ref = [s["op"].M(s["base"][k]) for k in range(2)]
-    for r in (0, 5, 23):
+    for r in range(NB):
         err = rel(y[r], PHASES[r] * ref[r % 2])
         print("fp64 dirac 32^3x64 rhs", r, "rel err", err)
         assert err <= 1e-12
 
 
 def test_fullsize_dirac_fp16_storage_batch():
+    """Member r of the batch is the FP32 rounding of phase_r x base; the
+    operator is linear, so the reference is phase_r x (oracle on base), and
+    the input rounding contributes at most 6e-8 of the 1e-5 bound."""
     torch, dfl = _gpu()
     s = state()
     x = batch(np.complex64)
     y = dfl.dirac_apply(s["fld"], torch.from_numpy(x).cuda(), storage=F16).cpu().numpy()
     q = quantised_operator(F16)
-    for r in (0, 23):
-        xr = x[r].astype(np.complex128)
-        err = rel(y[r], q.M(xr))
+    ref = [q.M(s["base"][k]) for k in range(2)]
+    for r in range(NB):
+        err = rel(y[r], PHASES[r] * ref[r % 2])
         print("fp16-storage dirac 32^3x64 rhs", r, "rel err", err)
         assert err <= 1e-5
 
 
 def test_fullsize_sap_fp16_storage_batch():
+    """M_SAP is homogeneous under complex scalars (each minimal-residual
+    coefficient (p, r)/(p, p) is unchanged when r and p are scaled by the
+    same phase), so every member is compared with phase_r x (oracle M_SAP of
+    the base spinor); the FP32 input rounding adds about 1e-7."""
     torch, dfl = _gpu()
     s = state()
     x = batch(np.complex64)
     psi = dfl.sap_precond(s["fld"], torch.from_numpy(x).cuda(), dfl.SapParams(5, 4, F16)).cpu().numpy()
     q = quantised_operator(F16)
-    for r in (0, 23):
-        ref = q.sap(x[r].astype(np.complex128), BLOCK, 5, 4)
-        err = rel(psi[r], ref)
+    ref = [q.sap(s["base"][k], BLOCK, 5, 4) for k in range(2)]
+    for r in range(NB):
+        err = rel(psi[r], PHASES[r] * ref[r % 2])
         print("fp16-storage sap 32^3x64 rhs", r, "rel err", err)
-        assert err <= SAP_TOL
+        assert err <= SAP_TOL_F16
 
 
 def test_fullsize_ama_residuals():
-    """Two source positions of the benchmark's set (the first also solved
-    exactly), deflated with the benchmark's subspace parameters."""
+    """The benchmark's solver parameters (deflation N_s = 12, n_inv = 5;
+    sloppy: FP16 storage, residual 3e-3, little budget 4; exact: FP32 SAP,
+    residual 1e-10, little budget 16; 24 right-hand sides per batch) on two
+    source positions of its set, the first also solved exactly.  The
+    oracle's FP64 operator recomputes the residual of all 12 spin-colour
+    solutions of both positions (sloppy, returned in FP32) and of the exact
+    position (returned in FP64)."""
     torch, dfl = _gpu()
     s = state()
     x0 = synth.seeded_site(DIMS, 1)
@@ -119,25 +132,33 @@ def test_fullsize_ama_residuals():
     positions = [(t0, a0, b0, c0), ((t0 + 16) % 64, a0, b0, (c0 + 16) % 32)]
     sloppy_sap, exact_sap = dfl.SapParams(5, 4, F16), dfl.SapParams(5, 4, F32)
     d = dfl.Deflation(s["fld"], Ns=12, ninv=5, seed=7, sap=sloppy_sap)
-    sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sloppy_sap, dfl=d, little_tol=1e-6, little_maxit=16)
+    sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sloppy_sap, dfl=d, little_tol=1e-6, little_maxit=4)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=exact_sap, dfl=d, little_tol=1e-10, little_maxit=16)
     xs, xe, infs, infe = dfl.ama_solve(s["fld"], positions, [True, False], sloppy, exact, dtype=torch.complex128,
-                                       batch=NB)
+                                       sloppy_dtype=torch.complex64, batch=NB)
     assert all(i.status == 0 for i in infs) and all(i.status == 0 for i in infe)
     op = s["op"]
+    worst = 0.0
     for g, pos in enumerate(positions):
         lex = synth.lex(DIMS, *pos)
-        xg = xs[g].cpu().numpy()
-        for sc in (0, 7):
+        xg = xs[g].cpu().numpy().astype(np.complex128)
+        for sc in range(12):
             eta = synth.point_source(DIMS, lex, sc)
             rr = oracle.norm(eta - op.M(xg[sc])) / oracle.norm(eta)
-            print("sloppy position", g, "sc", sc, "oracle residual", rr)
-            assert rr <= 3e-3
+            worst = max(worst, rr)
+            assert rr <= 3e-3, (g, sc, rr)
+            # the reported FP64 residual is the true one of the returned vector
+            # (up to the FP32 rounding of the output)
+            assert abs(infs[12 * g + sc].rel_res - rr) <= 1e-6 + 1e-3 * rr, (g, sc)
+    print("sloppy: worst oracle residual", worst)
     lex = synth.lex(DIMS, *positions[0])
     xe0 = xe[0].cpu().numpy()
-    for sc in (0, 11):
+    worst = 0.0
+    for sc in range(12):
         eta = synth.point_source(DIMS, lex, sc)
         rr = oracle.norm(eta - op.M(xe0[sc])) / oracle.norm(eta)
-        print("exact sc", sc, "oracle residual", rr)
-        assert rr <= 1.01e-10
+        worst = max(worst, rr)
+        assert abs(infe[sc].rel_res - rr) <= 1e-3 * rr, sc
+    print("exact: worst oracle residual", worst)
+    assert worst <= 1.01e-10
     d.close()

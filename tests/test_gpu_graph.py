@@ -173,3 +173,29 @@ def test_stencil_knobs_reject_bad_values():
                         (F.TUNE_STENCIL_ORDER, 0), (F.TUNE_STENCIL_BLOCK, 1)):
         fld.tune(knob, value)
     fld.close()
+
+
+def test_graph_cache_follows_the_workspace_layout():
+    """A graph captured for batches of 2 inside a 4-wide workspace (the tail
+    of 10 sources in batches of 4) writes its solutions at the 4-wide
+    layout's address; a later call with 2 sources lays the workspace out
+    2-wide, so it must capture its own graph rather than replay that one.
+    Both calls on one handle must give exactly what a fresh handle gives."""
+    torch, dfl = _gpu()
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    fld, d, p = make(U, torch, dfl)
+    b = sources(torch, dfl, fld)
+    dfl.gcr_solve_batched(fld, b, p, batch=4, graph=True)
+    two = [b[3].clone(), b[6].clone()]
+    x, info = dfl.gcr_solve_batched(fld, two, p, graph=True)
+    fld2, d2, p2 = make(U, torch, dfl)
+    xr, infor = dfl.gcr_solve_batched(fld2, [v.clone() for v in two], p2, graph=True)
+    for k in range(2):
+        assert torch.equal(x[k], xr[k]), k
+        assert info[k].rel_res == infor[k].rel_res
+    # and a replay of the 2-wide graph on the first handle
+    x3, _ = dfl.gcr_solve_batched(fld, two, p, graph=True)
+    for k in range(2):
+        assert torch.equal(x3[k], xr[k]), k
+    for h in (d2, fld2, d, fld):
+        h.close()

@@ -3,10 +3,14 @@
 FP64 paths must agree to 1e-12 relative per application; reduced-precision
 storage (FP32, FP16, BF16 links and clover, FP32 arithmetic) to 1e-5 per
 operator application against the oracle evaluated on identically quantised
-inputs.  M_SAP eta chains about n_cy (n_mr + 2) = 30 FP32 operator
-applications with data-dependent minimal-residual coefficients, so its FP32
-rounding bound is SAP_TOL = 30 x 1e-6 (a single FP32 application rounds to
-about 1e-6 relative here, well inside the 1e-5 per-application bound).
+inputs.  M_SAP eta chains about n_cy (n_mr + 2) = 30 operator applications
+with data-dependent minimal-residual coefficients.  Its bound depends on
+the storage (SAP_TOL): FP32 storage 1e-6 (FP32 arithmetic on FP32-rounded
+inputs; observed about 1e-7); FP16 storage 1e-5 (the per-application
+bound: both sides build the clover entries independently in FP64, and the
+few entries at an FP16 rounding boundary round to neighbouring values);
+BF16 storage 3e-5 (that floor plus the chain bound of about 30 FP32
+applications at 1e-6 each; observed about 1.1e-5 on the small lattices).
 """
 
 import numpy as np
@@ -19,7 +23,7 @@ from tests import quant
 pytestmark = pytest.mark.gpu
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
-SAP_TOL = 3e-5
+SAP_TOL = {F32: 1e-6, F16: 1e-5, BF16: 3e-5}
 
 
 def _gpu():
@@ -197,7 +201,7 @@ def test_sap_reduced_precision_matches_quantised_oracle(storage):
     ref = c.qop(storage).sap(eta.astype(np.complex128), c.block, 5, 4)
     for r in range(2):
         print("sap storage", storage, "rhs", r, "rel err", rel(psi[r], ref[r]))
-        assert rel(psi[r], ref[r]) <= SAP_TOL, (r, rel(psi[r], ref[r]))
+        assert rel(psi[r], ref[r]) <= SAP_TOL[storage], (r, rel(psi[r], ref[r]))
 
 
 @pytest.mark.parametrize("storage", [F32, F16])
@@ -218,7 +222,7 @@ def test_sap_paired_right_hand_sides(storage):
         c.field.tune(dfl.Field.TUNE_SAP_PAIR, 1)
     ref = c.qop(storage).sap(eta.cpu().numpy().astype(np.complex128), c.block, 5, 4)
     for r in range(4):
-        assert rel(paired[r], ref[r]) <= SAP_TOL and rel(single[r], ref[r]) <= SAP_TOL, r
+        assert rel(paired[r], ref[r]) <= SAP_TOL[storage] and rel(single[r], ref[r]) <= SAP_TOL[storage], r
         assert rel(paired[r], single[r]) <= 1e-5, (r, rel(paired[r], single[r]))
 
 
@@ -235,7 +239,7 @@ def test_sap_block_shapes(dims, block):
     psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), dfl.SapParams(5, 4, F32)).cpu().numpy()
     ref = c.qop(F32).sap(eta.astype(np.complex128), block, 5, 4)
     print("sap block", block, "rel err", rel(psi[0], ref[0]))
-    assert rel(psi[0], ref[0]) <= SAP_TOL
+    assert rel(psi[0], ref[0]) <= SAP_TOL[F32]
 
 
 def test_sap_point_source_and_single_cycle():

@@ -151,15 +151,32 @@ def dfl_pair():
 
 def test_deflation_fields_match_oracle_subspace(dfl_pair):
     """Same counter-based random fields and inverse iteration (FP32 SAP on the
-    GPU, FP64 in the oracle): the block subspaces agree to FP32 rounding."""
+    GPU, FP64 in the oracle).  The fields before orthonormalisation differ by
+    the FP32 rounding of the three M_SAP rounds (at most 1e-6 each, the FP32
+    Schwarz bound); an orthonormal basis of their span moves by at most that
+    perturbation times the condition number of the block's field matrix, so
+    the bound is 3e-6 x (largest block condition number)."""
     op, fld, d = dfl_pair
     phi = d.get_phi().cpu().numpy().reshape(d.Nb, d.Ns, -1)
     ref = oracle.Deflation(op, fld.block, Ns=8, ninv=3, seed=11)
     G = np.einsum("bki,bli->bkl", np.conj(phi), phi)
     assert np.abs(G - np.eye(d.Ns)[None]).max() < 1e-5
+    # the oracle's fields before Gram-Schmidt, restricted to the blocks
+    v = oracle.random_fields(op.V, 8, 11)
+    for _ in range(3):
+        v = op.sap(v, fld.block, 5, 4)
+        for l in range(8):
+            v[l] /= oracle.norm(v[l])
+    vb = v.reshape(8, op.V, 12)[:, ref.sites.reshape(-1), :].reshape(8, ref.Nb, -1).transpose(1, 0, 2)
+    # column scaling does not move the span: condition numbers of the
+    # block matrices with unit columns
+    vb = vb / np.linalg.norm(vb, axis=2, keepdims=True)
+    kappa = max(np.linalg.cond(vb[b].T) for b in range(ref.Nb))
     # subspace distance: residual of projecting the GPU basis onto the oracle's
     proj = np.einsum("bki,bkj,blj->bli", ref.phi, np.conj(ref.phi), phi)
-    assert np.linalg.norm(phi - proj) / np.linalg.norm(phi) < 1e-3
+    dist = np.linalg.norm(phi - proj) / np.linalg.norm(phi)
+    print("subspace distance", dist, "largest block condition number", kappa)
+    assert dist <= 3e-6 * kappa
 
 
 @pytest.fixture(scope="module")
@@ -208,7 +225,11 @@ def test_fp32_restrict_prolong_match_oracle(Ns, n):
     torch, dfl = _gpu()
     op, fld = setup(*DFL_KEY)
     d = dfl.Deflation(fld, Ns=Ns, ninv=1, seed=13, sap=dfl.SapParams(5, 4, F32))
-    phi = d.get_phi().cpu().numpy().reshape(d.Nb, d.Ns, -1)
+    # the basis comes from the oracle, rounded to FP32 (the GPU's storage),
+    # and is loaded into the handle; the oracle uses exactly those values
+    ref0 = oracle.Deflation(op, fld.block, Ns=Ns, ninv=1, seed=13)
+    phi = ref0.phi.astype(np.complex64).astype(np.complex128)
+    d.set_phi(torch.from_numpy(phi.reshape(d.Nb, d.Ns, -1, 4, 3)).cuda())
     ref = oracle.Deflation(op, fld.block, Ns=Ns, phi=phi)
     v = synth.gaussian_spinor(fld.dims, n, 2102).astype(np.complex64)
     u = d.restrict(torch.from_numpy(v).cuda()).cpu().numpy()
@@ -232,6 +253,17 @@ def test_little_solve_residual(dfl_given_phi):
         assert rel(w[r], ref.little_solve(v[r])) <= 1e-8
 
 
+def test_little_solve_rejects_more_than_4096_right_hand_sides(dfl_given_phi):
+    """Polled little solves read their norms through a pinned buffer of 4096
+    values: larger calls are refused before any launch."""
+    torch, dfl = _gpu()
+    op, fld, d, ref = dfl_given_phi
+    v = torch.zeros((4097, d.Nb, d.Ns), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dfl.DflError) as e:
+        d.little_solve(v)
+    assert e.value.code == -1
+
+
 def test_deflated_exact_solve_matches_oracle(dfl_given_phi):
     torch, dfl = _gpu()
     op, fld, d, ref = dfl_given_phi
@@ -249,11 +281,30 @@ def test_deflated_exact_solve_matches_oracle(dfl_given_phi):
     print("iterations deflated", info[0].iters, "undeflated", info0[0].iters)
 
 
+def _sigma_min_estimate(op, block, v, steps=2):
+    """Estimate of the smallest singular value of M by inverse iteration on
+    M^+ M with oracle solves: (M^+ M)^-1 = M^-1 g5 M^-1 g5 (gamma_5
+    hermiticity).  The Rayleigh quotient approaches the largest eigenvalue
+    of (M^+ M)^-1 from below, so 1/sqrt of it estimates sigma_min from above."""
+    g5 = np.array([1, 1, -1, -1], float)[None, :, None]
+    v = v / oracle.norm(v)
+    lam = 0.0
+    for _ in range(steps):
+        y, _ = oracle.solve(op, g5 * v, block=block, res=1e-8)
+        w, _ = oracle.solve(op, g5 * y, block=block, res=1e-8)
+        lam = float(np.real(oracle.vdot(v, w)))
+        v = w / oracle.norm(w)
+    return 1.0 / np.sqrt(lam)
+
+
 def test_config1_exact_deflated_solve():
     """16^3 x 32, eps 0.4, kappa 0.124, c_sw 1.5, SAP 4^4 with 4 MinRes steps,
     deflation Ns = 12 on 4^4 blocks, one point source, exact to 1e-10 with
-    FP64 outer and FP32 SAP.  The oracle's FP64 operator checks the residual;
-    the undeflated GPU solve is an independent second solution."""
+    FP64 outer and FP32 SAP.  The exact solution has a plain definition,
+    x = M^-1 b: the oracle's own FP64 solve to residual 1e-13 (undeflated, so
+    nothing of the GPU's subspace enters) is the reference, at 1e-8.  The
+    a-posteriori bound ||r|| / (sigma_min ||x||) is reported beside it, with
+    sigma_min estimated by two oracle inverse-iteration steps."""
     torch, dfl = _gpu()
     dims, block = (32, 16, 16, 16), (4, 4, 4, 4)
     op, fld = setup(dims, block, 0.4, 0.124, 1.5)
@@ -262,14 +313,46 @@ def test_config1_exact_deflated_solve():
     b = synth.point_source(dims, site, 0)[None]
     p = dfl.GcrParams(nkv=16, nmx=300, res=1e-10, sap=dfl.SapParams(5, 4, F32), dfl=d, little_tol=1e-10)
     x, info = dfl.gcr_solve(fld, torch.from_numpy(b).cuda(), p)
-    p0 = dfl.GcrParams(nkv=16, nmx=300, res=1e-10, sap=dfl.SapParams(5, 4, F32))
-    x0, info0 = dfl.gcr_solve(fld, torch.from_numpy(b).cuda(), p0)
-    x, x0 = x.cpu().numpy(), x0.cpu().numpy()
-    assert info[0].status == 0 and info0[0].status == 0
-    assert oracle_relres(op, x[0], b[0]) <= 1.05e-10
-    assert oracle_relres(op, x0[0], b[0]) <= 1.05e-10
-    assert rel(x[0], x0[0]) <= 1e-8
-    print("config1 iterations deflated", info[0].iters, "undeflated", info0[0].iters)
+    x = x.cpu().numpy()
+    assert info[0].status == 0
+    rr = oracle_relres(op, x[0], b[0])
+    assert rr <= 1.05e-10
+    xo, io = oracle.solve(op, b[0], block=block, res=1e-13)
+    assert io.status == 0
+    err = rel(x[0], xo)
+    smin = _sigma_min_estimate(op, block, synth.gaussian_spinor(dims, 1, 2201)[0])
+    bound = oracle.norm(b[0] - op.M(x[0])) / (smin * oracle.norm(x[0]))
+    print(f"config1: iterations {info[0].iters}, residual {rr:.2e}, error vs oracle {err:.2e}, "
+          f"sigma_min estimate {smin:.3e}, a-posteriori bound {bound:.2e}")
+    assert err <= 1e-8
+    d.close()
+
+
+def test_one_and_two_gcr_iterations_match_oracle_steps():
+    """Step parity of the flexible GCR (section 2.2): with fixed iteration
+    counts 1 and 2, undeflated, FP32 Schwarz preconditioner, the solution
+    x = sum_k alpha_k z_k equals the oracle's GCR run with the same steps on
+    the identically quantised FP32 operator (the GPU applies M with FP32
+    storage inside a cycle).  Each iteration adds one FP32 M_SAP chain (1e-6,
+    the FP32 Schwarz bound)."""
+    torch, dfl = _gpu()
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    op, fld = setup(dims, block, 0.4, 0.124, 1.5)
+    U = op.U
+    q = oracle.Operator(dims, quant.quantise_links(U, quant.STORAGE_KIND[F32]), op.kappa, op.csw, op.bc_t,
+                        Am=quant.quantise_clover(op.Am, quant.CLOVER_KIND[F32]))
+    q.Ainv = quant.quantise_clover(op.Ainv, quant.CLOVER_KIND[F32])
+    b = np.stack([synth.point_source(dims, 77, 5), synth.gaussian_spinor(dims, 1, 2202)[0]])
+    for it in (1, 2):
+        p = dfl.GcrParams(nkv=8, fixed_iters=it, res=1e-14, sap=dfl.SapParams(5, 4, F32))
+        x, info = dfl.gcr_solve(fld, torch.from_numpy(b).cuda(), p)
+        x = x.cpu().numpy()
+        for r in range(2):
+            xo, _ = oracle.gcr(q.M, lambda v: q.sap(v, block, 5, 4), b[r], nkv=8, fixed_iters=it)
+            err = rel(x[r], xo)
+            print("GCR iterations", it, "rhs", r, "error vs oracle steps", err)
+            assert info[r].iters == it
+            assert err <= it * 1e-6
 
 
 # ---------------------------------------------------------------------------
