@@ -114,6 +114,20 @@ int dirac_apply(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, q
 int dirac_apply_ex(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
                    qcd_prec spinor_in, qcd_prec spinor_out, hipStream_t stream);
 
+/* dirac_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same operator and arguments, with the input and output staged in the
+ * library's internal layout in a static device array of 64 MiB per GPU
+ * (held from the library's first use of that GPU until the process ends)
+ * instead of workspace that grows on demand; no device memory is allocated
+ * and no profiling events are created.  Staging needs 2 x nrhs x V x 96
+ * bytes (FP32 vectors; 192 with FP64 storage); a call that needs more than
+ * 64 MiB returns QCD_EINVAL.  Calls overlapping in time on one GPU share the
+ * array and must not be issued (they race).  The field's device must be
+ * current. */
+int dirac_apply_noalloc(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, qcd_prec storage,
+                        hipStream_t stream);
+
 /* Schwarz preconditioner psi = M_SAP eta (section 2.2): ncy cycles starting
  * from psi = 0; each cycle visits all blocks of colour 0 (Omega) in
  * parallel, then all blocks of colour 1 (Omega*).  A block visit computes the

@@ -89,6 +89,7 @@ def load():
     L.qcd_field_destroy.argtypes = [P]
     L.dirac_apply.argtypes = [P, P, P, I, I, I, P]
     L.dirac_apply_ex.argtypes = [P, P, P, I, I, I, I, I, P]
+    L.dirac_apply_noalloc.argtypes = [P, P, P, I, I, I, P]
     L.make_z2_sources.argtypes = [P, C.c_ulonglong, C.c_longlong, I, P, I, P]
     L.qcd_field_tune.argtypes = [P, I, I]
     L.gcr_solve_batched.argtypes = [P, C.POINTER(_Gcr), C.POINTER(P), C.POINTER(P), I, I, I, I, C.POINTER(_Info), P]
@@ -345,6 +346,17 @@ def dirac_apply(field: Field, x, storage: int = F64, out=None, spinor_in=None, s
     so = dflt if spinor_out is None else spinor_out
     _check(load().dirac_apply_ex(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _io_of(x),
                                  storage, si, so, _stream()), "dirac_apply_ex")
+    return out
+
+
+def dirac_apply_noalloc(field: Field, x, out, storage: int = F64):
+    """out = M x staged in the library's static scratch array (no device
+    allocation): x and out are preallocated GPU tensors of one shape."""
+    n = _vec(x, field.V)
+    if out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of x's shape and dtype")
+    _check(load().dirac_apply_noalloc(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n,
+                                      _io_of(x), storage, _stream()), "dirac_apply_noalloc")
     return out
 
 

@@ -672,6 +672,13 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     f->g = g;
     DFL_HIP(hipGetDevice(&f->device));
     {
+        const int rc = static_scratch_init(f->device);
+        if (rc < 0) {
+            delete f;
+            return rc;
+        }
+    }
+    {
         int lds = 0;
         DFL_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, f->device));
         f->lds_max = lds > 0 ? (size_t)lds : 64 * 1024;

@@ -705,6 +705,10 @@ int unpack_spinor(qcd_field f, const void *internal, qcd_prec vec, void *canon, 
 int z2_source_internal(qcd_field f, unsigned long long seed, long long index, double2 *b, hipStream_t s);
 int seq_source_internal(qcd_field f, const void *fwd, qcd_prec io, int t_sink, int mu, double2 *b, hipStream_t s);
 
+// device address of the static scratch array of dirac_apply_noalloc,
+// looked up once per device with that device current (at field creation)
+int static_scratch_init(int dev);
+
 // launch geometry helper: grid of g workgroups over n items
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
