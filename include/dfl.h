@@ -238,7 +238,9 @@ int gcr_solve(qcd_field f, const qcd_gcr *p, const void *b, void *x, int nrhs, q
  * 3.5, Table 3) run without host synchronisation, each batch size replayed
  * from one captured HIP graph; a solution the fixed count leaves above
  * sloppy.res is solved again with the residual-stopping solver (its info
- * then counts both solves' iterations).  Other solves stop at their res.
+ * then counts both solves' iterations); sloppy.res = 0 keeps every
+ * truncated solution as it is (the paper's fixed N_iter).  Other solves
+ * stop at their res.
  * Source vectors and outputs must not overlap.  Returns QCD_NOCONV when a
  * solution misses its target; errors as for gcr_solve. */
 typedef enum { QCD_SRC_POINT = 0, QCD_SRC_Z2 = 1, QCD_SRC_SEQ = 2, QCD_SRC_VEC = 3 } qcd_src_kind;
@@ -311,6 +313,59 @@ int make_z2_sources(qcd_field f, unsigned long long seed, long long index0, int 
  * the lattice give QCD_EINVAL. */
 int make_sequential_sources(qcd_field f, const void *psi, void *eta, int n, qcd_prec io, int t_sink, int mu,
                             hipStream_t stream);
+
+/* Nucleon correlators from point-source propagators (section 2.3) and the
+ * all-mode-averaging combination of observables (section 2.1).
+ *
+ * A propagator `prop` is the 12 canonical solutions x_j = M^{-1} b_j of the
+ * point sources b_j = delta_{x,x0} e_j, j = 3 spin + colour, at io precision
+ * (DEVICE, [12][V][4][3]); S(x)[s c][s' c'] = x_{3s'+c'}(x)[s c].  The
+ * nucleon field is N_al = eps_abc (u_a^T C gamma_5 d_b) u_{c,al} (eq. Nop)
+ * with C = gamma_0 gamma_2 in the operator's chiral basis and the conjugate
+ * Nbar = eps (ubar (dbar C gamma_5 ubar^T)); u and d are degenerate (both
+ * propagators are S) and no 2 kappa normalisation factor is applied.  All
+ * arithmetic is FP64; timeslice sums are reduced in a fixed order.
+ *
+ * nucleon_2pt: corr (DEVICE complex128 [T][4][4]) receives the zero-momentum
+ * two-point function G(t)_{al al'} = sum over the sites x of timeslice
+ * (t0 + t) mod T of <N_al(x) Nbar_al'(x0)> by Wick's theorem
+ *   eps_abc eps_a'b'c' [ S^{cc'} tr(Gamma S^{bb'} Gamma S^{aa' T})
+ *                        - S^{ca'} (Gamma S^{bb'} Gamma)^T S^{ac'} ],
+ * Gamma = C gamma_5; t0 is the source timeslice.  Projected correlators
+ * tr(P G(t)) use P+ = (1 + gamma_0)/2 forward and P- backward.
+ *
+ * nucleon_seq_sources: the 12 sequential sources of a three-point function
+ * with the nucleon sink on timeslice t_sink, zero momentum, projected with
+ * the spin matrix proj (HOST complex128 [4][4], row-major), for the current
+ * on the u line (flavour 0, both u lines) or the d line (flavour 1):
+ * eta_j(x)_i = gamma_5,ii conj(K(x)_{ij}) on t_sink and 0 elsewhere, where
+ * K = d tr(proj C(x)) / d S_flavour(x).  eta: DEVICE [12][V][4][3] at io
+ * precision, must not overlap prop.  The solutions Sigma_j = M^{-1} eta_j
+ * carry the sink back to every site (gamma_5-hermiticity); the forward and
+ * backward nucleons of the paper take t_sink = t0 + t_s with P+ and
+ * t0 - t_s with P-.
+ *
+ * nucleon_3pt: corr (DEVICE complex128 [T]) receives
+ *   sum over y of timeslice (t0 + t) mod T of
+ *   sum_j (gamma_5 Sigma_j(y))^+ (gamma_op x_j(y)),
+ * the three-point function with the current gamma_op (HOST complex128
+ * [4][4] spin matrix, identity in colour) inserted at time t, from the
+ * sequential propagators seqprop = Sigma and the propagator prop.
+ *
+ * ama_combine: out[k] = (1/n_org) sum_f (exact_f[f][k] - appx_f[f][k])
+ *   + (1/n_g) sum_g appx_g[g][k]   (eqs. caa1, caa2)
+ * for DEVICE complex128 arrays appx_g [n_g][len], exact_f and appx_f
+ * [n_org][len] (n_org may be 0), out [len]; observables of different
+ * sources must already be aligned (e.g. time relative to each source).
+ * Errors: null pointers, timeslices outside the lattice, bad flavour or
+ * sizes give QCD_EINVAL. */
+int nucleon_2pt(qcd_field f, const void *prop, qcd_prec io, int t0, void *corr, hipStream_t stream);
+int nucleon_seq_sources(qcd_field f, const void *prop, qcd_prec io, int t_sink, const double *proj, int flavour,
+                        void *eta, hipStream_t stream);
+int nucleon_3pt(qcd_field f, const void *seqprop, const void *prop, qcd_prec io, int t0, const double *gamma_op,
+                void *corr, hipStream_t stream);
+int ama_combine(long long len, int n_g, const void *appx_g, int n_org, const void *exact_f, const void *appx_f,
+                void *out, hipStream_t stream);
 
 /* Launch choices of a handle's Dirac stencil and Schwarz sweeps, for the
  * autotuner (defaults: block-staged, automatic, lexicographic, automatic,

@@ -109,6 +109,10 @@ def load():
         ("ama_solve", [P, C.POINTER(_Ama), C.POINTER(P), C.POINTER(P), I, C.POINTER(_Info), C.POINTER(_Info), P]),
         ("ama_solve_multi", [I, C.POINTER(P), C.POINTER(_Ama), C.POINTER(C.POINTER(P)), C.POINTER(C.POINTER(P)), I,
                              C.POINTER(C.POINTER(_Info)), C.POINTER(C.POINTER(_Info)), P]),
+        ("nucleon_2pt", [P, P, I, I, P, P]),
+        ("nucleon_seq_sources", [P, P, I, I, P, I, P, P]),
+        ("nucleon_3pt", [P, P, P, I, I, P, P, P]),
+        ("ama_combine", [C.c_longlong, I, P, I, P, P, P, P]),
         ("qcd_workspace_cached", [I, C.POINTER(C.c_size_t)]),
         ("qcd_workspace_trim", [I]),
         ("qcd_field_trim", [P]),
@@ -542,6 +546,75 @@ def ama_solve_multi(fields, sets, dtype=None, sloppy_dtype=None):
     rc = load().ama_solve_multi(nf, fh, amas, ps, pe, io, iS, iE, _stream())
     _check(rc, "ama_solve_multi", ok_noconv=True)
     return [(b[2], b[3], _infos(b[1]["info_s"], b[4]), _infos(b[1]["info_e"], b[5])) for b in built]
+
+
+def _prop(field, prop):
+    if _vec(prop, field.V) != 12:
+        raise ValueError("a propagator is 12 vectors [12, V, 4, 3]")
+    return _io_of(prop)
+
+
+def _spin_matrix(m):
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128).reshape(4, 4))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def nucleon_2pt(field: Field, prop, t0: int):
+    """G(t)[4, 4] (complex128, [T, 4, 4]) of the point-source propagator prop
+    [12, V, 4, 3] with source timeslice t0 (include/dfl.h, nucleon_2pt)."""
+    torch = _torch()
+    io = _prop(field, prop)
+    out = torch.empty((field.dims[0], 4, 4), dtype=torch.complex128, device="cuda")
+    _check(load().nucleon_2pt(field.handle, C.c_void_p(prop.data_ptr()), io, int(t0), C.c_void_p(out.data_ptr()),
+                              _stream()), "nucleon_2pt")
+    return out
+
+
+def nucleon_seq_sources(field: Field, prop, t_sink: int, proj, flavour: str):
+    """The 12 sequential sources [12, V, 4, 3] for a sink on t_sink with the
+    spin projector proj, current on the 'u' or 'd' line."""
+    torch = _torch()
+    io = _prop(field, prop)
+    out = torch.empty_like(prop)
+    _, pp = keep = _spin_matrix(proj)
+    _check(load().nucleon_seq_sources(field.handle, C.c_void_p(prop.data_ptr()), io, int(t_sink), pp,
+                                      {"u": 0, "d": 1}[flavour], C.c_void_p(out.data_ptr()), _stream()),
+           "nucleon_seq_sources")
+    del keep
+    return out
+
+
+def nucleon_3pt(field: Field, seqprop, prop, t0: int, gamma_op):
+    """sum_y sum_j (g5 Sigma_j(y))^+ gamma_op x_j(y) per timeslice relative to t0 ([T] complex128)."""
+    torch = _torch()
+    io = _prop(field, prop)
+    if _prop(field, seqprop) != io:
+        raise ValueError("sequential propagators and propagator must share the io dtype")
+    out = torch.empty((field.dims[0],), dtype=torch.complex128, device="cuda")
+    _, gp = keep = _spin_matrix(gamma_op)
+    _check(load().nucleon_3pt(field.handle, C.c_void_p(seqprop.data_ptr()), C.c_void_p(prop.data_ptr()), io,
+                              int(t0), gp, C.c_void_p(out.data_ptr()), _stream()), "nucleon_3pt")
+    del keep
+    return out
+
+
+def ama_combine(appx_g, exact_f=None, appx_f=None):
+    """O_AMA = mean_f (exact_f - appx_f) + mean_g appx_g (eqs. caa1, caa2) for
+    complex128 GPU tensors [n_g, ...], [n_org, ...], [n_org, ...]."""
+    torch = _torch()
+    for t in (appx_g, exact_f, appx_f):
+        if t is not None and (t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("observables must be contiguous complex128 GPU tensors")
+    n_g = appx_g.shape[0]
+    n_org = 0 if exact_f is None else exact_f.shape[0]
+    if n_org and (appx_f is None or appx_f.shape != exact_f.shape or exact_f.shape[1:] != appx_g.shape[1:]):
+        raise ValueError("exact_f and appx_f must have one shape, matching appx_g per observable")
+    out = torch.empty(appx_g.shape[1:], dtype=torch.complex128, device="cuda")
+    ln = out.numel()
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    _check(load().ama_combine(ln, n_g, ptr(appx_g), n_org, ptr(exact_f), ptr(appx_f), ptr(out), _stream()),
+           "ama_combine")
+    return out
 
 
 def workspace_cached(device: int = 0) -> int:

@@ -608,8 +608,8 @@ struct qcd_field_s {
     void *clo[3] = {nullptr, nullptr, nullptr};             // by CloFmt, all sites
     void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
     // scratch buffers owned by the handle, one per purpose, grown on demand
-    void *buf[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t buf_bytes[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    void *buf[10] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t buf_bytes[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
     unsigned graph_gen = 0;  // bumped whenever a scratch buffer moves (captured graphs refer to them)
     // stencil launch choices (autotuner knobs; defaults from the environment)
@@ -630,7 +630,7 @@ namespace dfl {
 // grow-only device scratch of a field handle, one buffer per purpose
 enum BufSlot {
     BUF_APPLY = 0, BUF_SAP = 1, BUF_GCR = 2, BUF_GCR_IO = 3, BUF_DFL = 4, BUF_AMA = 5, BUF_RED = 6, BUF_SAP_IO = 7,
-    BUF_RES = 8
+    BUF_RES = 8, BUF_CONTRACT = 9
 };
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
 // Solver mode without host synchronisation (for stream capture into a HIP
