@@ -367,6 +367,33 @@ int nucleon_3pt(qcd_field f, const void *seqprop, const void *prop, qcd_prec io,
 int ama_combine(long long len, int n_g, const void *appx_g, int n_org, const void *exact_f, const void *appx_f,
                 void *out, hipStream_t stream);
 
+/* Source and sink smearing (section 2.3: Gaussian smearing with APE-smeared
+ * gauge links in the Laplacian; the paper takes the parameters from earlier
+ * work, so they are arguments here).
+ *
+ * qcd_field_ape_smear: n_iter APE steps of the handle's spatial links, kept
+ * in the handle (FP64) for gauss_smear; time links are not smeared.  A step:
+ *   U'_i(x) = P[(1 - alpha) U_i(x) + (alpha/4) sum_{j != i spatial}
+ *             (U_j(x) U_i(x+j) U_j(x+i)^+ + U_j(x-j)^+ U_i(x-j) U_j(x-j+i))]
+ * with P the projection onto SU(3): the unitary polar factor W of its
+ * argument divided by exp(i arg(det W) / 3), arg in (-pi, pi].  n_iter = 0
+ * keeps the unsmeared links.  Errors: QCD_EINVAL (n_iter < 0), QCD_ENOMEM.
+ *
+ * qcd_field_get_ape_links: the smeared links as DEVICE complex128
+ * [V][3][3][3] (lexicographic site, direction i = mu - 1, row-major);
+ * QCD_ENOTSET before qcd_field_ape_smear.
+ *
+ * gauss_smear: out = S^n_iter in for nrhs canonical vectors (io precision,
+ * DEVICE; in and out may coincide), one step
+ *   psi'(x) = [psi(x) + kappa_g sum_{i spatial} (U'_i(x) psi(x+i)
+ *             + U'_i(x-i)^+ psi(x-i))] / (1 + 6 kappa_g),
+ * colour only, each timeslice on its own, periodic in space, FP64
+ * arithmetic.  QCD_ENOTSET before qcd_field_ape_smear. */
+int qcd_field_ape_smear(qcd_field f, double alpha, int n_iter, hipStream_t stream);
+int qcd_field_get_ape_links(qcd_field f, void *links, hipStream_t stream);
+int gauss_smear(qcd_field f, const void *in, void *out, int nrhs, qcd_prec io, double kappa_g, int n_iter,
+                hipStream_t stream);
+
 /* Launch choices of a handle's Dirac stencil and Schwarz sweeps, for the
  * autotuner (defaults: block-staged, automatic, lexicographic, automatic,
  * 1, 1):

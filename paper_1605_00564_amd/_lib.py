@@ -109,6 +109,9 @@ def load():
         ("ama_solve", [P, C.POINTER(_Ama), C.POINTER(P), C.POINTER(P), I, C.POINTER(_Info), C.POINTER(_Info), P]),
         ("ama_solve_multi", [I, C.POINTER(P), C.POINTER(_Ama), C.POINTER(C.POINTER(P)), C.POINTER(C.POINTER(P)), I,
                              C.POINTER(C.POINTER(_Info)), C.POINTER(C.POINTER(_Info)), P]),
+        ("qcd_field_ape_smear", [P, D, I, P]),
+        ("qcd_field_get_ape_links", [P, P, P]),
+        ("gauss_smear", [P, P, P, I, I, D, I, P]),
         ("nucleon_2pt", [P, P, I, I, P, P]),
         ("nucleon_seq_sources", [P, P, I, I, P, I, P, P]),
         ("nucleon_3pt", [P, P, P, I, I, P, P, P]),
@@ -237,6 +240,18 @@ class Field:
     def tune(self, knob: int, value: int):
         """Set a launch choice of the Dirac stencil (see include/dfl.h)."""
         _check(load().qcd_field_tune(self.handle, knob, value), "qcd_field_tune")
+
+    def ape_smear(self, alpha: float, n_iter: int):
+        """APE-smear the spatial links (kept in the handle for gauss_smear)."""
+        _check(load().qcd_field_ape_smear(self.handle, float(alpha), int(n_iter), _stream()), "qcd_field_ape_smear")
+
+    def ape_links(self):
+        """The smeared spatial links [V, 3, 3, 3] (complex128, direction mu - 1)."""
+        torch = _torch()
+        out = torch.empty((self.V, 3, 3, 3), dtype=torch.complex128, device="cuda")
+        _check(load().qcd_field_get_ape_links(self.handle, C.c_void_p(out.data_ptr()), _stream()),
+               "qcd_field_get_ape_links")
+        return out
 
     def trim(self):
         """Give this handle's scratch buffers to the workspace cache."""
@@ -546,6 +561,16 @@ def ama_solve_multi(fields, sets, dtype=None, sloppy_dtype=None):
     rc = load().ama_solve_multi(nf, fh, amas, ps, pe, io, iS, iE, _stream())
     _check(rc, "ama_solve_multi", ok_noconv=True)
     return [(b[2], b[3], _infos(b[1]["info_s"], b[4]), _infos(b[1]["info_e"], b[5])) for b in built]
+
+
+def gauss_smear(field: Field, x, kappa_g: float, n_iter: int, out=None):
+    """Gaussian smearing of the vectors x [n, V, 4, 3] with the handle's APE links."""
+    torch = _torch()
+    n = _vec(x, field.V)
+    out = torch.empty_like(x) if out is None else out
+    _check(load().gauss_smear(field.handle, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), n, _io_of(x),
+                              float(kappa_g), int(n_iter), _stream()), "gauss_smear")
+    return out
 
 
 def _prop(field, prop):

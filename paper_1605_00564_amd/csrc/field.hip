@@ -821,6 +821,7 @@ int qcd_field_destroy(qcd_field f) {
     for (auto p : f->U) (void)hipFree(p);
     for (auto p : f->clo) (void)hipFree(p);
     for (auto p : f->cloinv) (void)hipFree(p);
+    (void)hipFree(f->Uape);
     // scratch goes back to the workspace cache once queued work is done
     (void)hipDeviceSynchronize();
     graph_cache_free(f);

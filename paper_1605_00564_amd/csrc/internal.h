@@ -607,6 +607,7 @@ struct qcd_field_s {
     void *U[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // by LinkFmt
     void *clo[3] = {nullptr, nullptr, nullptr};             // by CloFmt, all sites
     void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
+    void *Uape = nullptr;    // APE-smeared spatial links, FP64 [3][9][V] (smearing of sources and sinks)
     // scratch buffers owned by the handle, one per purpose, grown on demand
     void *buf[10] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     size_t buf_bytes[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
