@@ -1,4 +1,5 @@
 // Field handle: geometry tables, link storage copies and the clover term.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -736,6 +737,37 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
             }
     }
     if (g.Vbh > 32767) return fail(set_error(QCD_EINVAL, "Schwarz block too large"));
+    // hops that leave a block, grouped by direction mu: the forward-face
+    // sites (both parities) first, then the backward-face ones; the two
+    // faces of one mu are disjoint because block extents are at least 2
+    std::vector<int> face[4];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int d = 0; d < 2; ++d)
+            for (int l = 0; l < g.Vb; ++l) {
+                int c[4], r = l;
+                for (int m = 3; m >= 0; --m) {
+                    c[m] = r % g.b[m];
+                    r /= g.b[m];
+                }
+                if (c[mu] != (d == 0 ? g.b[mu] - 1 : 0)) continue;
+                const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+                face[mu].push_back((p << 30) | (d << 29) | (l >> 1));
+            }
+    // within a face, parity-major and ascending j: consecutive lanes then
+    // read consecutive exchange-buffer rows of one parity (no bank conflicts)
+    for (int mu = 0; mu < 4; ++mu) std::sort(face[mu].begin(), face[mu].end(), [](int a, int b) {
+        const int da = (a >> 29) & 1, db = (b >> 29) & 1;
+        return da != db ? da < db : a < b;
+    });
+    f->face_cap = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        f->nface[mu] = (int)face[mu].size();
+        f->face_cap = std::max(f->face_cap, f->nface[mu]);
+    }
+    std::vector<int> fl((size_t)4 * f->face_cap, 0);
+    for (int mu = 0; mu < 4; ++mu) std::copy(face[mu].begin(), face[mu].end(), fl.begin() + (size_t)mu * f->face_cap);
+    if (!dev_alloc(f->device, (void **)&f->bface, sizeof(int) * fl.size()))
+        return fail(set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create"));
     // stencil launch defaults, overridable from the environment
     if (const char *e = getenv("DFL_STENCIL_BLOCK")) f->st_block = atoi(e);
     if (const char *e = getenv("DFL_STENCIL_RG")) f->st_rg = atoi(e);
@@ -757,6 +789,7 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         bord[Bl] = (bsum & 1) * (g.Nb / 2) + Bl / 2;
     }
     hipError_t e = hipMemcpyAsync(f->lnbr, lnb.data(), sizeof(short) * lnb.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->bface, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(f->border, bord.data(), sizeof(int) * bord.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
@@ -814,6 +847,7 @@ int qcd_field_destroy(qcd_field f) {
     if (!f) return 0;
     (void)hipFree(f->nbr);
     (void)hipFree(f->lnbr);
+    (void)hipFree(f->bface);
     (void)hipFree(f->border);
     (void)hipFree(f->int_of);
     (void)hipFree(f->lex_of);

@@ -601,6 +601,11 @@ struct qcd_field_s {
     int device = 0;
     int *nbr = nullptr;      // [8][V], direction d = 2*mu + (0 fwd | 1 bwd)
     short *lnbr = nullptr;   // [2 parity][Vbh][8]: in-block neighbour (local j) or -1; same for every block
+    // hops leaving a block, per direction mu: entries (parity << 30 | fwd 0 / bwd 1 << 29 | j),
+    // [4][face_cap], nface[mu] used; the same for every block
+    int *bface = nullptr;
+    int nface[4] = {0, 0, 0, 0};
+    int face_cap = 0;
     int *int_of = nullptr;   // [V] lexicographic -> internal
     int *lex_of = nullptr;   // [V] internal -> lexicographic
     int *border = nullptr;   // [Nb] lexicographic block -> block index in memory (colour-major)
@@ -609,8 +614,8 @@ struct qcd_field_s {
     void *cloinv[3] = {nullptr, nullptr, nullptr};          // by CloFmt, odd sites
     void *Uape = nullptr;    // APE-smeared spatial links, FP64 [3][9][V] (smearing of sources and sinks)
     // scratch buffers owned by the handle, one per purpose, grown on demand
-    void *buf[10] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t buf_bytes[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    void *buf[11] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t buf_bytes[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     int *flag = nullptr;     // device status word
     unsigned graph_gen = 0;  // bumped whenever a scratch buffer moves (captured graphs refer to them)
     // stencil launch choices (autotuner knobs; defaults from the environment)
@@ -631,7 +636,7 @@ namespace dfl {
 // grow-only device scratch of a field handle, one buffer per purpose
 enum BufSlot {
     BUF_APPLY = 0, BUF_SAP = 1, BUF_GCR = 2, BUF_GCR_IO = 3, BUF_DFL = 4, BUF_AMA = 5, BUF_RED = 6, BUF_SAP_IO = 7,
-    BUF_RES = 8, BUF_CONTRACT = 9
+    BUF_RES = 8, BUF_CONTRACT = 9, BUF_SAP_RES = 10
 };
 int field_buffer(qcd_field f, int slot, size_t bytes, void **p);
 // Solver mode without host synchronisation (for stream capture into a HIP

@@ -2,15 +2,28 @@
 //
 // One launch = one colour sweep: every workgroup owns one Schwarz block of
 // that colour and one right-hand side.  It forms the block residual
-// rho = eta - M psi (neighbour values from the other colour), solves the
-// Dirichlet block equation approximately with nmr minimal-residual steps on
-// the even-odd reduced block operator
+// rho = eta - M psi, solves the Dirichlet block equation approximately with
+// nmr minimal-residual steps on the even-odd reduced block operator
 //     Dhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe
 // and adds the correction to psi.  Thread t owns the even site j = t and the
 // odd site j = t of the block (and j = t + NT when KS = 2).  The two
 // exchange vectors of the MinRes iteration (r on even sites, t = A_oo^{-1}
 // H_oe r on odd sites) live in LDS when they fit, else in a per-workgroup
 // global buffer; everything else stays in registers.
+//
+// The block residual is kept up to date instead of recomputed.  After a
+// block's update its residual equals the final minimal-residual vector on
+// the block's even sites, and rho_o + kappa H_oe x_e - A_oo delta_o on its
+// odd sites (zero when the stored inverse clover is the exact inverse of the
+// stored clover; at FP16 storage it is not); both are stored (`res`).  Until the
+// block is visited again only the blocks of the other colour change, by
+// their corrections delta (stored in `dlt` by every sweep), and they enter
+// the block's residual only through the hops that cross its faces:
+//     rho_block = res_block + kappa H_{block <- neighbours} delta.
+// The first cycle starts from rho = eta (psi = 0).  The face hops of a block
+// are listed per direction mu (block-face table, the same for every block):
+// all threads of the workgroup take one direction per round, so no two of
+// them touch the same site in a round and no lane waits on another's branch.
 #include "internal.h"
 
 namespace dfl {
@@ -61,34 +74,37 @@ __device__ inline void block_hop(const void *U, const short *lnbr, long V, long 
 #undef DFL_BHOP
 }
 
-// (M psi)(x) with the full neighbourhood (neighbours read from global psi)
-template <class S, class R, int LF, int CF>
-__device__ inline void full_dirac_site(const void *psi, const void *U, const void *clo, const int *nbr, long V,
-                                       long x, R kappa, cx<R> out[12], unsigned qoff = 0) {
-    cx<R> acc[12], w[9], p[12];
+// kappa times the hops into the block across one face direction MU of the
+// block, from the corrections of the neighbouring blocks, added to the LDS
+// (or global) exchange buffers: entry (parity, fwd/bwd, j) of the face table
+template <class S, class R, int LF, int MU>
+__device__ inline void face_round(const int *bface, int fcap, int nf, int tid, int NT, const void *U, const int *nbr,
+                                  const void *dlt, unsigned qoff, long V, long Vh, long boff, int Vbh, R kappa,
+                                  cx<R> *Rb, cx<R> *Tb) {
+    for (int k = tid; k < nf; k += NT) {
+        const int ent = bface[MU * fcap + k];
+        const int par = ent >> 30, bwd = (ent >> 29) & 1, j = ent & 0x1fffffff;
+        const unsigned x = (unsigned)(par * Vh + boff + j);
+        cx<R> w[9], p[12], acc[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
-#define DFL_FHOP(MU)                                          \
-    {                                                         \
-        const int ef = nbr_at(nbr, 2 * MU, V, x);                 \
-        Link<LF>::load(U, V, MU, x, w);                       \
-        Spin<S>::load(psi, V, nb_index(ef) + qoff, p);        \
-        hop<R, MU, true>(w, p, nb_sign<R>(ef), acc);          \
-        const int eb = nbr_at(nbr, 2 * MU + 1, V, x);             \
-        Link<LF>::load(U, V, MU, nb_index(eb), w);            \
-        Spin<S>::load(psi, V, nb_index(eb) + qoff, p);        \
-        hop<R, MU, false>(w, p, nb_sign<R>(eb), acc);         \
+        for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+        const int e = nbr_at(nbr, 2 * MU + bwd, V, x);
+        const unsigned y = nb_index(e);
+        Spin<S>::load(dlt, V, y + qoff, p);
+        if (!bwd) {
+            Link<LF>::load(U, V, MU, x, w);
+            hop<R, MU, true>(w, p, nb_sign<R>(e), acc);
+        } else {
+            Link<LF>::load(U, V, MU, y, w);
+            hop<R, MU, false>(w, p, nb_sign<R>(e), acc);
+        }
+        cx<R> *buf = par ? Tb : Rb;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) buf[c * Vbh + j] = rmac(buf[c * Vbh + j], kappa, acc[c]);
     }
-    DFL_FHOP(0)
-    DFL_FHOP(1)
-    DFL_FHOP(2)
-    DFL_FHOP(3)
-#undef DFL_FHOP
-    Spin<S>::load(psi, V, x + qoff, p);
-    clover_apply<CF>(clo, V, x, p, out);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) out[k] = rmac(out[k], -kappa, acc[k]);
 }
+
+enum SweepFlags { SW_FIRST = 1, SW_FACES = 2, SW_STORE_RES = 4, SW_STORE_DLT = 8 };
 
 // VBHC > 0: the block's sites per parity as a compile-time constant (the
 // component planes of the exchange buffers then sit at immediate LDS
@@ -101,10 +117,14 @@ __device__ inline void full_dirac_site(const void *psi, const void *U, const voi
 // index (qr x NCH x V chunks further).
 template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0, int NR = 1>
 __global__ void __launch_bounds__(MAXT)
-    k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, const void *__restrict__ U,
-                const void *__restrict__ clo, const void *__restrict__ cinv, const int *__restrict__ nbr,
-                const short *__restrict__ lnbr, long V, long Vh, int Vbh_arg, int nbc, int colour, R kappa, int nmr,
-                int first, cx<R> *gbuf) {
+    k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, void *__restrict__ res_all,
+                void *__restrict__ dlt_all, const void *__restrict__ U, const void *__restrict__ clo,
+                const void *__restrict__ cinv, const int *__restrict__ nbr, const short *__restrict__ lnbr,
+                const int *__restrict__ bface, int fcap, int4 nface, long V, long Vh, int Vbh_arg, int nbc, int colour,
+                R kappa, int nmr, int flags, cx<R> *gbuf) {
+    // flags: SW_FIRST: first cycle (rho starts from eta, psi is zero on this
+    // colour); SW_FACES: add the neighbours' corrections across the faces;
+    // SW_STORE_RES: keep the even-site residual; SW_STORE_DLT: keep the correction
     static_assert(NR == 1 || (LDS && KS == 1 && Spin<S>::NCH * 16 == Spin<S>::BYTES), "NR = 2 layout");
     constexpr int SPW = 64 / NR;   // sites per wave
     const int Vbh = VBHC > 0 ? VBHC : Vbh_arg;
@@ -119,7 +139,10 @@ __global__ void __launch_bounds__(MAXT)
     const size_t fs = (size_t)Spin<S>::BYTES * V;
     const void *eta = wave_uniform(static_cast<const char *>(eta_all) + (size_t)rg * NR * fs);
     void *psi = wave_uniform(static_cast<char *>(psi_all) + (size_t)rg * NR * fs);
-    const unsigned qoff = (unsigned)(qr * Spin<S>::NCH * V);  // its offset, in chunks
+    void *dlt = wave_uniform(static_cast<char *>(dlt_all) + (size_t)rg * NR * fs);
+    void *res = wave_uniform(static_cast<char *>(res_all) + (size_t)rg * NR * fs);
+    const unsigned qoff = (unsigned)(qr * Spin<S>::NCH * V);    // its offset, in chunks
+    const bool first = flags & SW_FIRST, keep_dlt = flags & SW_STORE_DLT;
     const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
     cx<R> *Rb, *Tb;
@@ -131,36 +154,53 @@ __global__ void __launch_bounds__(MAXT)
     Tb = Rb + 12 * Vbh;
 
     cx<R> xe[KS][12];
-    // ---- block residual rho = eta - M psi: rho_e into R, s_o = A_oo^{-1} rho_o into T ----
+    // ---- block residual: eta (first cycle) or the stored residual, then the
+    //      neighbours' corrections across the faces ----
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
         if (j < Vbh) {
             const long xe_i = boff + j, xo_i = Vh + boff + j;
-            cx<R> e[12], m[12];
-            Spin<S>::load(eta, V, xe_i + qoff, e);
-            if (!first) {
-                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xe_i, kappa, m, qoff);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
-            }
+            cx<R> e[12];
+            const void *src = first ? eta : res;
+            Spin<S>::load(src, V, xe_i + qoff, e);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = e[c];
-            Spin<S>::load(eta, V, xo_i + qoff, e);
-            if (!first) {
-                full_dirac_site<S, R, LF, CF>(psi, U, clo, nbr, V, xo_i, kappa, m, qoff);
+            Spin<S>::load(src, V, xo_i + qoff, e);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) e[c] = e[c] - m[c];
-            }
+            for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = e[c];
+        }
+    }
+    if (flags & SW_FACES) {
+        __syncthreads();
+        face_round<S, R, LF, 0>(bface, fcap, nface.x, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        __syncthreads();
+        face_round<S, R, LF, 1>(bface, fcap, nface.y, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        __syncthreads();
+        face_round<S, R, LF, 2>(bface, fcap, nface.z, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        __syncthreads();
+        face_round<S, R, LF, 3>(bface, fcap, nface.w, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        __syncthreads();
+    }
+    // ---- s_o = A_oo^{-1} rho_o into T (rho_o kept for the odd residual) ----
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int j = tid + k * NT;
+        if (j < Vbh) {
+            cx<R> e[12], m[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) e[c] = Tb[c * Vbh + j];
+            if (flags & SW_STORE_RES) Spin<S>::store(res, V, Vh + boff + j + qoff, e);
             clover_apply<CF>(cinv, Vh, boff + j, e, m);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = m[c];
         }
     }
     __syncthreads();
-    // ---- r = rhat_e = rho_e + kappa H_eo s_o ; x_e = 0 ; psi_o += s_o ----
-    // (every read of this block's psi happened before the barrier above, and
-    //  no other workgroup of this colour reads this block)
+    // ---- r = rhat_e = rho_e + kappa H_eo s_o ; x_e = 0 ; s_o kept (psi_o or
+    //      the stored correction) ----
+    // (the neighbour blocks' corrections were read before the barriers above,
+    //  and no other workgroup of this colour touches this block)
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
@@ -173,15 +213,19 @@ __global__ void __launch_bounds__(MAXT)
                 xe[k][c] = {R(0), R(0)};
             }
             const long xo_i = Vh + boff + j;
-            if (first) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = Tb[c * Vbh + j];
+            for (int c = 0; c < 12; ++c) q[c] = Tb[c * Vbh + j];
+            if (keep_dlt) {
+                // delta_o = s_o + kappa A^-1 H_oe x_e is completed at the end
+                Spin<S>::store(dlt, V, xo_i + qoff, q);
             } else {
-                Spin<S>::load(psi, V, xo_i + qoff, q);
+                if (!first) {
+                    Spin<S>::load(psi, V, xo_i + qoff, acc);   // acc is no longer needed
 #pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = q[c] + Tb[c * Vbh + j];
+                    for (int c = 0; c < 12; ++c) q[c] = q[c] + acc[c];
+                }
+                Spin<S>::store(psi, V, xo_i + qoff, q);
             }
-            Spin<S>::store(psi, V, xo_i + qoff, q);
         }
     }
     __syncthreads();
@@ -240,32 +284,46 @@ __global__ void __launch_bounds__(MAXT)
             s2 += red[w][qr][2];
         }
         const cx<R> alpha = s2 > R(0) ? cx<R>{s0 / s2, s1 / s2} : cx<R>{R(0), R(0)};
+        const bool last = it + 1 == nmr;
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int j = tid + k * NT;
             if (j < Vbh) {
+                if (last && (flags & SW_STORE_RES)) {
+                    // the block's residual after the update: the new r on even sites
+                    cx<R> rn[12];
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) rn[c] = cmac(Rb[c * Vbh + j], -alpha, p[k][c]);
+                    Spin<S>::store(res, V, boff + j + qoff, rn);
+                }
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     const cx<R> rc = Rb[c * Vbh + j];
                     xe[k][c] = cmac(xe[k][c], alpha, rc);
-                    Rb[c * Vbh + j] = it + 1 < nmr ? cmac(rc, -alpha, p[k][c]) : xe[k][c];
+                    Rb[c * Vbh + j] = last ? xe[k][c] : cmac(rc, -alpha, p[k][c]);
                 }
             }
         }
         __syncthreads();
     }
     if (nmr == 0) {
-        // x_e = 0: publish it for the back substitution
+        // x_e = 0: the residual is rhat_e; publish x_e for the back substitution
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int j = tid + k * NT;
-            if (j < Vbh)
+            if (j < Vbh) {
+                cx<R> rn[12];
 #pragma unroll
-                for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = {R(0), R(0)};
+                for (int c = 0; c < 12; ++c) {
+                    rn[c] = Rb[c * Vbh + j];
+                    Rb[c * Vbh + j] = {R(0), R(0)};
+                }
+                if (flags & SW_STORE_RES) Spin<S>::store(res, V, boff + j + qoff, rn);
+            }
         }
         __syncthreads();
     }
-    // ---- psi_o += kappa A_oo^{-1} H_oe x_e ; psi_e += x_e ----
+    // ---- delta_o = s_o + kappa A_oo^{-1} H_oe x_e, delta_e = x_e; psi += delta ----
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
@@ -274,9 +332,32 @@ __global__ void __launch_bounds__(MAXT)
             cx<R> acc[12], t[12], q[12];
             block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
             clover_apply<CF>(cinv, Vh, boff + j, acc, t);
-            Spin<S>::load(psi, V, xo_i + qoff, q);
+            if (keep_dlt) {
+                Spin<S>::load(dlt, V, xo_i + qoff, q);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);
+                for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);   // delta_o
+                Spin<S>::store(dlt, V, xo_i + qoff, q);
+                Spin<S>::store(dlt, V, xe_i + qoff, xe[k]);
+                if (flags & SW_STORE_RES) {
+                    // odd residual rho_o + kappa H_oe x_e - A_oo delta_o (the
+                    // correction is kept whenever the residual is)
+                    clover_apply<CF>(clo, V, xo_i, q, t);
+                    cx<R> r[12];
+                    Spin<S>::load(res, V, xo_i + qoff, r);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) r[c] = rmac(r[c], kappa, acc[c]) - t[c];
+                    Spin<S>::store(res, V, xo_i + qoff, r);
+                }
+                if (!first) {
+                    Spin<S>::load(psi, V, xo_i + qoff, t);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) q[c] = q[c] + t[c];
+                }
+            } else {
+                Spin<S>::load(psi, V, xo_i + qoff, q);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);
+            }
             Spin<S>::store(psi, V, xo_i + qoff, q);
             if (first) {
                 Spin<S>::store(psi, V, xe_i + qoff, xe[k]);
@@ -288,18 +369,6 @@ __global__ void __launch_bounds__(MAXT)
             }
         }
     }
-}
-
-// psi = 0 on the sites of one colour (the first sweep writes the other colour)
-template <class S>
-__global__ void k_zero_colour(void *psi_all, long V, long Vh, long half, long cstart) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * half) return;
-    const long idx = (t < half ? 0 : Vh) + cstart + (t < half ? t : t - half);
-    const size_t fs = (size_t)Spin<S>::BYTES * V;
-    cx<float> z[12];
-    for (int c = 0; c < 12; ++c) z[c] = {0.f, 0.f};
-    Spin<S>::store(static_cast<char *>(psi_all) + blockIdx.y * fs, V, idx, z);
 }
 
 template <class S, class R, int LF, int CF>
@@ -322,50 +391,64 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
         DFL_TRY(field_buffer(f, BUF_SAP, (size_t)nbc * nrhs * lds, &p));
         gbuf = static_cast<cx<R> *>(p);
     }
+    // the blocks' stored even-site residuals and the last sweep's corrections
+    void *rp;
+    const size_t rbytes = (size_t)Spin<S>::BYTES * g.V * nrhs, dbytes = rbytes;
+    DFL_TRY(field_buffer(f, BUF_SAP_RES, rbytes + dbytes, &rp));
+    void *res = rp, *dlt = static_cast<char *>(rp) + rbytes;
     const R kappa = (R)f->lat.kappa;
-    const long half = (long)nbc * Vbh;
+    const int4 nface = make_int4(f->nface[0], f->nface[1], f->nface[2], f->nface[3]);
     const bool pair = sizeof(S) == 4 && f->st_sap_pair && use_lds && Vbh == 128 && NT == 128 && nrhs % 2 == 0;
     // Algorithmic work of one sweep per (even, odd) site pair of the swept
     // colour, with h = 165 flop per hop times the hops that stay inside the
-    // block (sum over mu of 2 (b_mu - 1) / b_mu per site):
-    //   residual 2 x (1872 + 24) (not in the first sweep), s_o = A^-1 rho_o 504,
-    //   rhat_e h + 72, each MinRes step 2h + 1392, back substitution h + 576.
-    // Compulsory bytes: eta, psi in (not first) and out, 4 links and the clover
-    // term per site, the inverse clover per odd site.
-    double hops = 0;
-    for (int m = 0; m < 4; ++m) hops += 2.0 * (g.b[m] - 1) / g.b[m];
-    const double h = 165.0 * hops;
+    // block (sum over mu of 2 (b_mu - 1) / b_mu per site) and nf the hops
+    // that cross the block's faces per pair (sum over mu of 4 / b_mu):
+    //   neighbours' corrections nf (165 + 24) (not in the first sweep),
+    //   s_o = A^-1 rho_o 504, rhat_e h + 72, each MinRes step 2h + 1392,
+    //   back substitution and correction h + 576, odd residual 552 (when kept).
+    // Compulsory bytes per pair: eta (first cycle) or the stored residual,
+    // the neighbours' corrections across the faces, psi in (after the first
+    // cycle) and out, the stored residual and correction out; 4 links and the
+    // clover term per site, the inverse clover per odd site.
+    double hops = 0, nf = 0;
+    for (int m = 0; m < 4; ++m) {
+        hops += 2.0 * (g.b[m] - 1) / g.b[m];
+        nf += 4.0 / g.b[m];
+    }
+    const double h = 165.0 * hops, B = Spin<S>::BYTES;
     const double lbytes = LF == LNK_F64 ? 144 : (LF == LNK_F16 || LF == LNK_BF16) ? 24 : 48;
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
     const double pairs = (double)nbc * Vbh * nrhs;
-    {
-        ProfScope pz(PROF_OTHER, s);
-        // colour 1 sites must start from zero; colour 0 is written by the first sweep
-        k_zero_colour<S><<<dim3(nblocks(2 * half, 256), nrhs), 256, 0, s>>>(psi, g.V, g.Vh, half, half);
-    }
     for (int cy = 0; cy < ncy; ++cy)
         for (int col = 0; col < 2; ++col) {
-            const int first = (cy == 0 && col == 0) ? 1 : 0;
+            int flags = 0;
+            if (cy == 0) flags |= SW_FIRST;
+            if (cy > 0 || col == 1) flags |= SW_FACES;
+            if (cy + 1 < ncy) flags |= SW_STORE_RES;
+            if (!(cy + 1 == ncy && col == 1)) flags |= SW_STORE_DLT;
             dim3 grid(nbc, nrhs);
-            const double fl = pairs * ((first ? 0.0 : 3792.0) + 504 + (h + 72) + nmr * (2 * h + 1392) + (h + 576));
-            const double by = pairs * (2.0 * Spin<S>::BYTES * (first ? 2 : 3)) + (double)nbc * Vbh * 2 *
-                              (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
+            const double fl = pairs * (((flags & SW_FACES) ? nf * 189.0 : 0.0) + 504 + (h + 72) +
+                                       nmr * (2 * h + 1392) + (h + 576) + ((flags & SW_STORE_RES) ? 552 : 0));
+            const double by = pairs * (B * (2 + ((flags & SW_FACES) ? nf : 0) + (cy == 0 ? 2 : 4) +
+                                            ((flags & SW_STORE_RES) ? 2 : 0) + ((flags & SW_STORE_DLT) ? 2 : 0))) +
+                              (double)nbc * Vbh * 2 * (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
             ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
+#define DFL_SAP_ARGS                                                                                             \
+    eta, psi, res, dlt, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, f->bface, f->face_cap, nface, g.V, \
+        g.Vh, Vbh, nbc, col, kappa, nmr, flags, gbuf
 #define DFL_SAP_LAUNCH(LDSV, KSV, MAXT, VBHC)                                                                  \
     {                                                                                                          \
         auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT, VBHC>;                                          \
         size_t sh = LDSV ? lds : 0;                                                                            \
         if (LDSV && sh > 64 * 1024) (void)hipFuncSetAttribute((const void *)kern,                              \
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
-        kern<<<grid, NT, sh, s>>>(eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, g.V, g.Vh, Vbh, nbc, col, \
-                                  kappa, nmr, first, gbuf);                                                    \
+        kern<<<grid, NT, sh, s>>>(DFL_SAP_ARGS);                                                               \
     }
             if constexpr (sizeof(S) == 4) {
                 // two right-hand sides per workgroup (4^4 blocks, even count)
                 if (pair) {
                     k_sap_sweep<S, R, LF, CF, true, 1, 256, 128, 2><<<dim3(nbc, nrhs / 2), 2 * NT, 2 * lds, s>>>(
-                        eta, psi, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, g.V, g.Vh, Vbh, nbc, col, kappa,
-                        nmr, first, gbuf);
+                        DFL_SAP_ARGS);
                     continue;
                 }
             }
@@ -379,6 +462,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
                 else DFL_SAP_LAUNCH(false, 2, 1024, 0)
             }
 #undef DFL_SAP_LAUNCH
+#undef DFL_SAP_ARGS
         }
     DFL_HIP(hipGetLastError());
     return 0;
