@@ -162,15 +162,57 @@ def reunitarise(U: np.ndarray) -> np.ndarray:
     return np.stack([r0, r1, r2], axis=-2)
 
 
+def expi_traceless_hermitian(Q: np.ndarray) -> np.ndarray:
+    """exp(i Q) for traceless Hermitian 3x3 matrices Q[..., 3, 3].
+
+    Cayley-Hamilton form exp(iQ) = f0 + f1 Q + f2 Q^2 with the coefficients
+    of Morningstar and Peardon (Phys. Rev. D 69 (2004) 054501, eqs. 29-36):
+    c0 = det Q, c1 = tr(Q^2)/2, theta = arccos(c0 / c0max),
+    u = sqrt(c1/3) cos(theta/3), w = sqrt(c1) sin(theta/3), and for c0 < 0
+    the coefficients of -Q with f_j(-c0) = (-1)^j conj(f_j(c0)).  Elementwise
+    array operations only (no per-matrix library loop).
+    """
+    Q2 = Q @ Q
+    c1 = 0.5 * np.real(np.trace(Q2, axis1=-2, axis2=-1))
+    c0 = np.real(np.trace(Q2 @ Q, axis1=-2, axis2=-1)) / 3.0
+    neg = c0 < 0
+    c0a = np.abs(c0)
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    ratio = np.where(c0max > 0, c0a / np.where(c0max > 0, c0max, 1.0), 0.0)
+    theta = np.arccos(np.clip(ratio, -1.0, 1.0))
+    u = np.sqrt(c1 / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1) * np.sin(theta / 3.0)
+    w2 = w * w
+    small = np.abs(w) < 0.05
+    xi0 = np.where(small, 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0)),
+                   np.sin(w) / np.where(small, 1.0, w))
+    e2iu = np.exp(2j * u)
+    emiu = np.exp(-1j * u)
+    cw = np.cos(w)
+    u2 = u * u
+    h0 = (u2 - w2) * e2iu + emiu * (8.0 * u2 * cw + 2j * u * (3.0 * u2 + w2) * xi0)
+    h1 = 2.0 * u * e2iu - emiu * (2.0 * u * cw - 1j * (3.0 * u2 - w2) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9.0 * u2 - w2
+    tiny = den < 1e-300
+    den = np.where(tiny, 1.0, den)
+    f0 = np.where(tiny, 1.0, h0 / den)
+    f1 = np.where(tiny, 1j, h1 / den)
+    f2 = np.where(tiny, -0.5, h2 / den)
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    eye = np.eye(3, dtype=np.complex128)
+    return f0[..., None, None] * eye + f1[..., None, None] * Q + f2[..., None, None] * Q2
+
+
 def su3_from_gaussian(omega: np.ndarray, eps: float) -> np.ndarray:
     """U = exp(i eps H), H = sum_a omega_a lambda_a / 2, for omega[..., 8]."""
     lam = gell_mann()
-    H = np.einsum("...a,aij->...ij", omega.astype(np.complex128), lam) * 0.5
+    sh = omega.shape[:-1]
+    H = (omega.reshape(-1, 8).astype(np.complex128) @ lam.reshape(8, 9)).reshape(sh + (3, 3)) * 0.5
     H = 0.5 * (H + np.conj(np.swapaxes(H, -1, -2)))
-    w, vec = np.linalg.eigh(H)
-    ph = np.exp(1j * eps * w)
-    U = np.einsum("...ik,...k,...jk->...ij", vec, ph, np.conj(vec))
-    return reunitarise(U)
+    return reunitarise(expi_traceless_hermitian(eps * H))
 
 
 def gauge_field(dims, eps: float, seed: int = 1, progress=None) -> np.ndarray:

@@ -1,0 +1,75 @@
+"""The 48^3 x 96 configuration at its stated size: eps 0.4, kappa 0.1245,
+c_sw 1.5, deflation N_s = 20 on 6^4 blocks, BF16 link storage with FP32
+arithmetic in the sloppy solves, FP64 outer GCR; the 12 spin-colour point
+sources of one position and 12 sequential sources (gamma_5 gamma_3 gamma_5
+insertion on timeslice t0 + 16, section 2.3), each solved sloppily (3e-3)
+and exactly (1e-10).  The sequential sources are built from 12 vectors made
+on the host (so that no oracle input comes from the GPU): the solver treats
+them exactly as it treats forward solutions.  The oracle's FP64 operator
+recomputes the residual of sampled solutions of every set."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+DIMS, BLOCK = (96, 48, 48, 48), (6, 6, 6, 6)
+KAPPA, CSW = 0.1245, 1.5
+
+
+def test_config3_full_size_point_and_sequential_sets(capsys):
+    import time
+    import torch
+    import paper_1605_00564_amd as dfl
+    t0 = time.time()
+
+    def say(msg):
+        # progress while the test runs (a full-size step takes tens of seconds)
+        with capsys.disabled():
+            print(f"[config3 {time.time() - t0:6.1f} s] {msg}", flush=True)
+
+    U = synth.gauge_field(DIMS, 0.4, 1)
+    say("gauge field generated")
+    fld = dfl.Field(DIMS, BLOCK, KAPPA, CSW, torch.from_numpy(U).cuda())
+    sap_s, sap_e = dfl.SapParams(5, 4, BF16), dfl.SapParams(5, 4, F32)
+    d = dfl.Deflation(fld, Ns=20, ninv=5, seed=7, sap=sap_s)
+    sloppy = dfl.GcrParams(nkv=8, nmx=30, res=3e-3, sap=sap_s, dfl=d, little_tol=1e-6, little_maxit=4)
+    exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap_e, dfl=d, little_tol=1e-10, little_maxit=16)
+    x0 = synth.seeded_site(DIMS, 1)
+    pos = tuple(int(v) for v in synth.coords(DIMS, x0))
+    t_sink = (pos[0] + 16) % DIMS[0]
+    fwd = synth.gaussian_spinor(DIMS, 12, 3301)
+    fwd_d = torch.from_numpy(fwd).cuda()
+    say("field handle and deflation subspace built")
+    xs, xe, infs, infe = dfl.ama_solve(fld, [dfl.point(pos), dfl.sequential(fwd_d, t_sink, 3)], [True, True],
+                                       sloppy, exact, dtype=torch.complex128, sloppy_dtype=torch.complex64)
+    say(f"solves done; iterations sloppy {sorted({i.iters for i in infs})}, exact {sorted({i.iters for i in infe})}")
+    assert all(i.status == 0 for i in infs + infe)
+    del fwd_d
+    op = oracle.Operator(DIMS, U, KAPPA, CSW, -1)
+    del U
+    say("oracle operator built")
+    seq = oracle.sequential_source(fwd, DIMS, t_sink, 3)
+    del fwd
+    sources = [lambda sc: synth.point_source(DIMS, x0, sc), lambda sc: seq[sc]]
+    for s, (src, tol) in enumerate(((sources[0], 3e-3), (sources[1], 3e-3))):
+        for sc in (0, 5, 11):
+            eta = src(sc)
+            x = xs[s][sc].cpu().numpy().astype(np.complex128)
+            rr = oracle.norm(eta - op.M(x)) / oracle.norm(eta)
+            say(f"sloppy set {s} sc {sc}: oracle residual {rr:.3e}, reported {infs[12 * s + sc].rel_res:.3e}")
+            assert rr <= tol
+    for s, src in enumerate(sources):
+        for sc in (0, 7):
+            eta = src(sc)
+            x = xe[s][sc].cpu().numpy()
+            rr = oracle.norm(eta - op.M(x)) / oracle.norm(eta)
+            say(f"exact set {s} sc {sc}: oracle residual {rr:.3e}")
+            assert rr <= 1.01e-10
+    say("done")
+    d.close()
+    fld.close()
