@@ -261,7 +261,8 @@ typedef struct {
     const unsigned char *exact;    /* host [nsrc] or NULL: nonzero = also solve exactly */
     qcd_gcr sloppy, exact_params;
     qcd_prec sloppy_out;           /* QCD_F64 or QCD_F32 */
-    int batch;                     /* right-hand sides per solver launch (0: library choice) */
+    int batch;                     /* right-hand sides per solver launch (0: library choice); lowered
+                                      to what 60% of the free device memory holds */
 } qcd_ama;
 
 int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const *x_exact, qcd_prec io,
@@ -273,7 +274,9 @@ int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const 
  * ama_solve.  Every field's handle keeps its own block shape, deflation
  * subspace, launch choices and captured graphs (an autotuner sets them per
  * field beforehand).  All sets are validated before the first launch; the
- * fields are then solved in order on `stream`.  All handles must live on
+ * fields are then solved in order on `stream`, each field's solver work
+ * buffers (and captured graphs) released to the library's cache once its
+ * set is done, so the peak memory is that of the largest field.  All handles must live on
  * the current device. */
 int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, void *const *const *x_sloppy,
                     void *const *const *x_exact, qcd_prec io, qcd_info *const *info_sloppy,
@@ -287,7 +290,8 @@ int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, vo
  * synchronisation, and its launches for one batch size are captured once
  * into a HIP graph (on a stream the handle owns) and replayed for every
  * later batch of that size, on `stream`.  Little solves inside then run
- * their fixed budget (p->little_maxit).  info[r].rel_res is the FP64
+ * a fixed budget: p->little_maxit iterations in P_R, and one cycle of
+ * max(24, p->little_maxit) iterations in the low-mode correction.  info[r].rel_res is the FP64
  * relative residual after the fixed iterations; status QCD_NOCONV if it is
  * above p->res.  Graphs are kept in the handle until a workspace buffer
  * grows or the handle is destroyed.  Calls must not overlap in time with

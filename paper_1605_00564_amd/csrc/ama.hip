@@ -85,19 +85,24 @@ int check_set(const Geom &g, const qcd_ama *a) {
 }
 
 // default right-hand sides per batch: as many as fit a modest share of HBM
+// right-hand sides per launch: as many as 60% of the free device memory
+// (plus the library's cached workspace) holds for these parameters, at most
+// 48 and a multiple of 12 when possible; a caller's request is lowered to
+// that bound (memory only: per right-hand side the results do not depend
+// on the batch)
 int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
-    if (want > 0) return want;
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
         (void)hipGetLastError();
-        return 12;
+        return want > 0 ? want : 12;
     }
     freeb += ws_cached_bytes(f->device);   // cached workspace is reusable
     const size_t V = f->g.V;
     const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
     const size_t per = V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5);
-    size_t n = (size_t)(0.6 * (double)freeb) / std::max<size_t>(per, 1);
-    n = std::min<size_t>(std::max<size_t>(n, 1), 48);
+    const size_t fit = std::max<size_t>((size_t)(0.6 * (double)freeb) / std::max<size_t>(per, 1), 1);
+    if (want > 0) return (int)std::min<size_t>((size_t)want, fit);
+    size_t n = std::min<size_t>(fit, 48);
     if (n >= 12) n -= n % 12;
     return (int)n;
 }
@@ -273,9 +278,13 @@ extern "C" int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_am
             return set_error(QCD_EINVAL, "all gauge fields of one call must live on one device");
     }
     int status = 0;
-    for (int k = 0; k < nfield; ++k)
+    for (int k = 0; k < nfield; ++k) {
         DFL_TRY(run_set(fields[k], sets[k], x_sloppy[k], x_exact[k], io, info_sloppy ? info_sloppy[k] : nullptr,
                         info_exact ? info_exact[k] : nullptr, s, status));
+        // a finished field's solver buffers go back to the workspace cache,
+        // so that the next field (of another size) can take their room
+        if (k + 1 < nfield) DFL_TRY(qcd_field_trim(fields[k]));
+    }
     DFL_HIP(hipStreamSynchronize(s));
     return status;
 }
