@@ -362,25 +362,55 @@ def block_mgs(phi, tol=1e-10):
 
 
 class Deflation:
-    """Deflation subspace Phi, little operator A and the projectors."""
+    """Deflation subspace Phi, little operator A and the projectors.
 
-    def __init__(self, op: Operator, block, Ns, ninv=5, seed=7, ncy=5, nmr=4, phi=None):
+    block: the deflation block; sap_block: the Schwarz block of the M_SAP
+    inverse iteration (default: the deflation block; the paper ties the two,
+    the library allows a deflation block made of several Schwarz blocks).
+    nref > 0: after the ninv rounds of v <- M_SAP v, nref rounds of the
+    inverse iteration v <- M^{-1} v (each field normalised), the solves done
+    by the deflated solver on the current subspace to relative residual
+    ref_res, each round followed by a new subspace and little operator
+    (section 2.2: inverse iteration refined with the deflated solver)."""
+
+    def __init__(self, op: Operator, block, Ns, ninv=5, seed=7, ncy=5, nmr=4, phi=None, sap_block=None,
+                 nref=0, ref_res=1e-2):
         self.op = op
         self.block = tuple(int(b) for b in block)
+        self.sap_block = tuple(int(b) for b in sap_block) if sap_block is not None else self.block
         self.Ns = int(Ns)
         self.sites = block_sites(op.dims, self.block)       # [Nb, Vb]
         self.nbr = block_neighbours(op.dims, self.block)    # [Nb, 9]
         self.Nb, self.Vb = self.sites.shape
         self.N = self.Nb * self.Ns
+        self.fields = None
         if phi is None:
             v = random_fields(op.V, self.Ns, seed)
             for _ in range(ninv):                          # inverse iteration with M_SAP
-                v = op.sap(v, self.block, ncy, nmr)
+                v = op.sap(v, self.sap_block, ncy, nmr)
                 for l in range(self.Ns):
                     v[l] /= norm(v[l])
-            vb = v.reshape(self.Ns, op.V, 12)[:, self.sites.reshape(-1), :]
-            vb = vb.reshape(self.Ns, self.Nb, self.Vb * 12).transpose(1, 0, 2)
-            phi = block_mgs(vb)
+            phi = self._orthonormal_blocks(v)
+            self.fields = v
+        elif nref:
+            raise ValueError("refinement starts from generated global fields")
+        self._set_phi(phi)
+        for _ in range(nref):                              # inverse iteration with the deflated solver
+            v = self.fields.copy()
+            for l in range(self.Ns):
+                x, _ = solve(op, v[l], self.sap_block, ncy, nmr, dfl=self, res=ref_res)
+                v[l] = x / norm(x)
+            self.fields = v
+            self._set_phi(self._orthonormal_blocks(v))
+
+    def _orthonormal_blocks(self, v):
+        """Global fields v[Ns, V, 4, 3] restricted to the blocks, then block MGS."""
+        vb = v.reshape(self.Ns, self.op.V, 12)[:, self.sites.reshape(-1), :]
+        vb = vb.reshape(self.Ns, self.Nb, self.Vb * 12).transpose(1, 0, 2)
+        return block_mgs(vb)
+
+    def _set_phi(self, phi):
+        op = self.op
         self.phi = np.ascontiguousarray(phi.reshape(self.Nb, self.Ns, self.Vb * 12), np.complex128)
         self.A = np.zeros((self.Nb, 9, self.Ns, self.Ns), np.complex128)
         rc = lib().orc_little_op(_p(_dims(op.dims)), op.kappa, op.bc_t, _p(_dims(self.block)), self.Ns,
