@@ -558,6 +558,10 @@ def main():
     ap.add_argument("--block", default="4,4,4,4")
     ap.add_argument("--ns", type=int, default=12)
     ap.add_argument("--ninv", type=int, default=5)
+    ap.add_argument("--dfl-block", default="", help="deflation block t,x,y,z (default: the Schwarz block)")
+    ap.add_argument("--nref", type=int, default=0,
+                    help="rounds of inverse iteration with the deflated solver refining the subspace")
+    ap.add_argument("--ref-res", type=float, default=1e-2, help="residual of the refinement solves")
     ap.add_argument("--no-deflation", action="store_true")
     ap.add_argument("--sweep-block-ns", default="",
                     help="one AMA step per block shape and N_s, e.g. '4,4,4,4:8,12,20;8,4,4,4:8,12,20'")
@@ -622,6 +626,7 @@ def main():
     work = WORKLOADS[args.workload]
     dims = work["dims"]
     block = tuple(int(b) for b in args.block.split(","))
+    dblock = tuple(int(b) for b in args.dfl_block.split(",")) if args.dfl_block else None
     V = synth.volume(dims)
     pos = positions(work, block)
     npos = len(pos)
@@ -651,7 +656,8 @@ def main():
         t1 = time.perf_counter()
         d = None
         if not args.no_deflation:
-            d = dfl.Deflation(fld, Ns=ns, ninv=args.ninv, seed=7, sap=sap_sloppy)
+            d = dfl.Deflation(fld, Ns=ns, ninv=args.ninv, seed=7, sap=sap_sloppy,
+                              block=dblock, nref=args.nref, ref_res=args.ref_res)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         # fixed > 0: truncated solves of `fixed` iterations from captured
@@ -772,7 +778,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": "x".join(str(d) for d in dims), "block": list(block),
-                   "Ns": 0 if args.no_deflation else args.ns, "positions": npos, "sloppy_rhs": 12 * npos,
+                   "Ns": 0 if args.no_deflation else args.ns, "positions": npos,
+                   "deflation_block": list(dblock or block), "nref": args.nref, "sloppy_rhs": 12 * npos,
                    "exact_rhs": 12, "sloppy_res": 3e-3, "exact_res": 1e-10,
                    "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage], "ncy": 5, "nmr": 4,
                    "little_maxit": {"sloppy": args.little_maxit_sloppy, "exact": args.little_maxit}},

@@ -147,22 +147,35 @@ int sap_precond(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int
 /* Block-local deflation (section 2.2): Ns global fields, drawn as complex
  * Gaussians from the counter-based generator SplitMix64 (key derived from
  * seed), refined by ninv rounds of the inverse iteration phi <- M_SAP phi
- * (normalised), restricted to the blocks and orthonormalised per block by
- * two passes of modified Gram-Schmidt.  The little operator
+ * (normalised), restricted to the deflation blocks and orthonormalised per
+ * block by two passes of modified Gram-Schmidt.  The little operator
  * A_kl = (phi_k, M phi_l) (eq. little) is assembled in FP64 with its
- * nearest-neighbour block structure, and its diagonal blocks are inverted. */
+ * nearest-neighbour block structure, and its diagonal blocks are inverted.
+ * Then nref further rounds of the inverse iteration phi <- M^{-1} phi
+ * (normalised), each solve done by the deflated SAP-GCR solver on the
+ * current subspace to relative residual ref_res (section 2.2: the inverse
+ * iteration refined with the deflated solver), each round followed by a new
+ * subspace and little operator.
+ * The deflation block defaults to the Schwarz block (the paper ties the two
+ * for simplicity); block[] may instead give a multiple of the Schwarz block
+ * in every direction, with an even number of deflation blocks along each
+ * axis (else QCD_EGEOM).  Ns > 12 x deflation-block volume: QCD_ESINGULAR. */
 typedef struct {
     int Ns;
     int ninv;
     unsigned long long seed;
-    qcd_sap sap;           /* preconditioner used by the inverse iteration */
+    qcd_sap sap;           /* preconditioner of the inverse iteration (and of the refinement solves) */
+    int block[4];          /* deflation block (t, x, y, z); all 0: the Schwarz block */
+    int nref;              /* rounds of inverse iteration with the deflated solver (0: none) */
+    double ref_res;        /* relative residual of those solves, in (0, 1) */
 } qcd_dfl_params;
 
 int deflation_setup(qcd_field f, const qcd_dfl_params *p, hipStream_t stream, qcd_dfl *out);
 int deflation_destroy(qcd_dfl d);
-/* Deflation fields as complex128 DEVICE buffer [Nb][Ns][Vb][4][3]: block B
- * in lexicographic order of the block grid, site j of the block in
- * lexicographic order of local coordinates. */
+/* Deflation fields as complex128 DEVICE buffer [Nb][Ns][Vb][4][3]: deflation
+ * block B in lexicographic order of the deflation-block grid, site j of the
+ * block (Vb = deflation-block volume) in lexicographic order of local
+ * coordinates. */
 int deflation_get_phi(qcd_dfl d, void *phi, hipStream_t stream);
 /* Replace the fields (same layout; must be block-orthonormal) and rebuild
  * the little operator; lets a caller supply a known basis. */

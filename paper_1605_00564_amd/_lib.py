@@ -42,7 +42,8 @@ class _Sap(C.Structure):
 
 
 class _DflParams(C.Structure):
-    _fields_ = [("Ns", C.c_int), ("ninv", C.c_int), ("seed", C.c_ulonglong), ("sap", _Sap)]
+    _fields_ = [("Ns", C.c_int), ("ninv", C.c_int), ("seed", C.c_ulonglong), ("sap", _Sap), ("block", C.c_int * 4),
+                ("nref", C.c_int), ("ref_res", C.c_double)]
 
 
 class _Gcr(C.Structure):
@@ -270,12 +271,18 @@ class Field:
 
 
 class Deflation:
-    """Block-local deflation subspace and little Dirac operator."""
+    """Block-local deflation subspace and little Dirac operator.  block: the
+    deflation block (default: the field's Schwarz block; else a multiple of
+    it); nref rounds of inverse iteration with the deflated solver to
+    relative residual ref_res refine the subspace (include/dfl.h,
+    deflation_setup)."""
 
-    def __init__(self, field: Field, Ns: int, ninv: int = 5, seed: int = 7, sap: SapParams = None):
+    def __init__(self, field: Field, Ns: int, ninv: int = 5, seed: int = 7, sap: SapParams = None, block=None,
+                 nref: int = 0, ref_res: float = 1e-2):
         L = load()
         sap = sap or SapParams()
-        p = _DflParams(int(Ns), int(ninv), int(seed), sap.c())
+        blk = (C.c_int * 4)(*([int(b) for b in block] if block is not None else [0, 0, 0, 0]))
+        p = _DflParams(int(Ns), int(ninv), int(seed), sap.c(), blk, int(nref), float(ref_res))
         h = C.c_void_p()
         _check(L.deflation_setup(field.handle, C.byref(p), _stream(), C.byref(h)), "deflation_setup")
         self.handle = h
@@ -283,15 +290,18 @@ class Deflation:
         nb, ns = C.c_int(), C.c_int()
         _check(L.deflation_dims(h, C.byref(nb), C.byref(ns)), "deflation_dims")
         self.Nb, self.Ns = nb.value, ns.value
+        self.Vb = field.V // self.Nb        # deflation-block volume
 
     def get_phi(self):
         torch = _torch()
-        Vb = int(np.prod(self.field.block))
-        phi = torch.empty((self.Nb, self.Ns, Vb, 4, 3), dtype=torch.complex128, device="cuda")
+        phi = torch.empty((self.Nb, self.Ns, self.Vb, 4, 3), dtype=torch.complex128, device="cuda")
         _check(load().deflation_get_phi(self.handle, C.c_void_p(phi.data_ptr()), _stream()), "deflation_get_phi")
         return phi
 
     def set_phi(self, phi):
+        torch = _torch()
+        if phi.dtype != torch.complex128 or not phi.is_cuda or phi.numel() != self.Nb * self.Ns * self.Vb * 12:
+            raise ValueError("phi must be a complex128 GPU tensor [Nb, Ns, Vb, 4, 3]")
         phi = phi.contiguous()
         _check(load().deflation_set_phi(self.handle, C.c_void_p(phi.data_ptr()), _stream()), "deflation_set_phi")
 

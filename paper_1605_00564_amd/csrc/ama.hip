@@ -24,6 +24,28 @@ __global__ void k_point_sources(double2 *__restrict__ b, const int *__restrict__
     b[((size_t)slot * 12 + sc) * V + int_of[lex]] = make_double2(1.0, 0.0);
 }
 
+// right-hand sides per launch: as many as 60% of the free device memory
+// (plus the library's cached workspace) holds for these parameters, at most
+// 48 and a multiple of 12 when possible; a caller's request is lowered to
+// that bound (memory only: per right-hand side the results do not depend
+// on the batch)
+int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
+        (void)hipGetLastError();
+        return want > 0 ? want : 12;
+    }
+    freeb += ws_cached_bytes(f->device);   // cached workspace is reusable
+    const size_t V = f->g.V;
+    const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
+    const size_t per = V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5);
+    const size_t fit = std::max<size_t>((size_t)(0.6 * (double)freeb) / std::max<size_t>(per, 1), 1);
+    if (want > 0) return (int)std::min<size_t>((size_t)want, fit);
+    size_t n = std::min<size_t>(fit, 48);
+    if (n >= 12) n -= n % 12;
+    return (int)n;
+}
+
 namespace {
 
 // one right-hand side of a set: vector k of source src
@@ -85,28 +107,6 @@ int check_set(const Geom &g, const qcd_ama *a) {
 }
 
 // default right-hand sides per batch: as many as fit a modest share of HBM
-// right-hand sides per launch: as many as 60% of the free device memory
-// (plus the library's cached workspace) holds for these parameters, at most
-// 48 and a multiple of 12 when possible; a caller's request is lowered to
-// that bound (memory only: per right-hand side the results do not depend
-// on the batch)
-int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
-    size_t freeb = 0, total = 0;
-    if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
-        (void)hipGetLastError();
-        return want > 0 ? want : 12;
-    }
-    freeb += ws_cached_bytes(f->device);   // cached workspace is reusable
-    const size_t V = f->g.V;
-    const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
-    const size_t per = V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5);
-    const size_t fit = std::max<size_t>((size_t)(0.6 * (double)freeb) / std::max<size_t>(per, 1), 1);
-    if (want > 0) return (int)std::min<size_t>((size_t)want, fit);
-    size_t n = std::min<size_t>(fit, 48);
-    if (n >= 12) n -= n % 12;
-    return (int)n;
-}
-
 size_t canon_bytes(qcd_prec p, long V) { return (p == QCD_F64 ? 16 : 8) * (size_t)12 * V; }
 
 // b64[0..n) = sources of list[r0 .. r0+n)

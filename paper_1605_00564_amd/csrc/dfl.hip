@@ -48,29 +48,65 @@ __global__ void k_normalise(float4 *__restrict__ v, long ne, const double *__res
     v[(size_t)blockIdx.y * ne + t] = make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
 }
 
-// global fields [Ns][6][V] -> block storage phi[B][l][6][2][Vbh]
+// A deflation block is the union of r Schwarz blocks (r = 1 when the two
+// sizes are tied).  Element q of one of its vectors (12 r Vbh float4, the
+// member Schwarz blocks one after the other, each in the (chunk, parity, j)
+// order) -> FP32 chunk c and internal site index; boff[B r + m] is the
+// internal offset (memory rank x Vbh) of member m of deflation block B.
+__device__ inline long dfl_site(const int *__restrict__ boff, int B, int r, int Vbh, long Vh, long q, int &c) {
+    const long per_b = 12L * Vbh;
+    const int m = (int)(q / per_b);
+    const long qq = q - (long)m * per_b;
+    c = (int)(qq / (2 * Vbh));
+    const int p = (int)((qq / Vbh) % 2), j = (int)(qq % Vbh);
+    return p * Vh + boff[(long)B * r + m] + j;
+}
+
+// global fields [Ns][6][V] -> block storage phi[B][l][12 r Vbh]
 __global__ void k_to_blocks(const float4 *__restrict__ v, float4 *__restrict__ phi, const int *__restrict__ boff,
-                            long V, long Vh, int Vbh, int Ns, int Nb) {
+                            long V, long Vh, int Vbh, int r, int Ns, int Nb) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long per = 12L * Vbh;
+    const long per = 12L * Vbh * r;
     if (t >= (long)Nb * Ns * per) return;
     const long q = t % per;
     const long bl = t / per;
     const int l = (int)(bl % Ns), B = (int)(bl / Ns);
-    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-    phi[t] = v[((size_t)l * 6 + c) * V + p * Vh + boff[B] + j];
+    int c;
+    const long site = dfl_site(boff, B, r, Vbh, Vh, q, c);
+    phi[t] = v[((size_t)l * 6 + c) * V + site];
 }
 
 // phi_l of every block as one global FP32 field [6][V]
 __global__ void k_phi_field(const float4 *__restrict__ phi, int l, float4 *__restrict__ out, const int *__restrict__ boff,
-                            long V, long Vh, int Vbh, int Ns, int Nb) {
+                            long V, long Vh, int Vbh, int r, int Ns, int Nb) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long per = 12L * Vbh;
+    const long per = 12L * Vbh * r;
     if (t >= (long)Nb * per) return;
     const int B = (int)(t / per);
     const long q = t % per;
-    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-    out[(size_t)c * V + p * Vh + boff[B] + j] = phi[((size_t)B * Ns + l) * per + q];
+    int c;
+    const long site = dfl_site(boff, B, r, Vbh, Vh, q, c);
+    out[(size_t)c * V + site] = phi[((size_t)B * Ns + l) * per + q];
+}
+
+// FP32 internal vectors [n][6][V] <-> FP64 internal vectors [n][12][V]
+__global__ void k_widen(const float4 *__restrict__ in, double2 *__restrict__ out, long V) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * V) return;
+    const long c = t / V, x = t - c * V;
+    const float4 a = in[(size_t)blockIdx.y * 6 * V + t];
+    double2 *o = out + (size_t)blockIdx.y * 12 * V;
+    o[(size_t)(2 * c) * V + x] = make_double2(a.x, a.y);
+    o[(size_t)(2 * c + 1) * V + x] = make_double2(a.z, a.w);
+}
+
+__global__ void k_narrow(const double2 *__restrict__ in, float4 *__restrict__ out, long V) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * V) return;
+    const long c = t / V, x = t - c * V;
+    const double2 *i = in + (size_t)blockIdx.y * 12 * V;
+    const double2 a = i[(size_t)(2 * c) * V + x], b = i[(size_t)(2 * c + 1) * V + x];
+    out[(size_t)blockIdx.y * 6 * V + t] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
 }
 
 template <int NV>
@@ -94,9 +130,9 @@ __device__ inline void wg_sum(double v[NV], double out[NV]) {
     __syncthreads();
 }
 
-// two passes of modified Gram-Schmidt over l inside each block (one workgroup per block)
-__global__ void __launch_bounds__(256) k_block_mgs(float4 *__restrict__ phi, int Ns, int Vbh, int *flag) {
-    const long per = 12L * Vbh;
+// two passes of modified Gram-Schmidt over l inside each deflation block
+// (one workgroup per block; per = float4 elements of one block vector)
+__global__ void __launch_bounds__(256) k_block_mgs(float4 *__restrict__ phi, int Ns, long per, int *flag) {
     float4 *base = phi + (size_t)blockIdx.x * Ns * per;
     for (int l = 0; l < Ns; ++l) {
         float4 *pl = base + (size_t)l * per;
@@ -151,15 +187,17 @@ __global__ void __launch_bounds__(256) k_block_mgs(float4 *__restrict__ phi, int
 }
 
 // Direction-resolved operator on a FP32 field (FP64 arithmetic):
-// out[0] = clover + hops inside the block, out[1 + 2 mu + dir] = -kappa times
-// the single hop (mu, dir) when it leaves the block (zero otherwise).
+// out[0] = clover + hops inside the deflation block, out[1 + 2 mu + dir] =
+// -kappa times the single hop (mu, dir) when it leaves the deflation block
+// (zero otherwise).  dbof: deflation block of each Schwarz block (by memory
+// rank, the site's internal index within its parity / Vbh).
 __global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ in, double2 *__restrict__ out,
                                                      const void *__restrict__ U, const void *__restrict__ clo,
-                                                     const int *__restrict__ nbr, long V, long Vh, int Vbh,
-                                                     double kappa) {
+                                                     const int *__restrict__ nbr, const int *__restrict__ dbof,
+                                                     long V, long Vh, int Vbh, double kappa) {
     const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= V) return;
-    const long bx = (x >= Vh ? x - Vh : x) / Vbh;
+    const long bx = dbof[(x >= Vh ? x - Vh : x) / Vbh];
     cx<double> acc[12], w[9], p[12], h[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
@@ -167,7 +205,7 @@ __global__ void __launch_bounds__(128) k_dirac_split(const float4 *__restrict__ 
     {                                                                                        \
         const int e = nbr_at(nbr, 2 * MU + (FWD ? 0 : 1), V, x);                                 \
         const long y = nb_index(e);                                                          \
-        const long by = (y >= Vh ? y - Vh : y) / Vbh;                                        \
+        const long by = dbof[(y >= Vh ? y - Vh : y) / Vbh];                                  \
         Link<LNK_F64>::load(U, V, MU, FWD ? x : y, w);                                       \
         Spin<float>::load(in, V, y, p);                                                      \
         const int d = 1 + 2 * MU + (FWD ? 0 : 1);                                            \
@@ -204,14 +242,13 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict__ v, const float4 *__restrict__ phi,
                                                        const int *__restrict__ boff, double2 *__restrict__ u, long V,
-                                                       long Vh, int Vbh, int Ns, int Nb, int n) {
+                                                       long Vh, int Vbh, int rb, int Ns, int Nb, int n) {
     __shared__ float red[4][16][17];
     const int B = blockIdx.x, r0 = blockIdx.y * 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
     const int col = lane & 15, rr = col >> 1, which = col & 1;
-    const long per = 12L * Vbh;
-    const long bo = boff[B];
+    const long per = 12L * Vbh * rb;
     const bool rv = r0 + rr < n;
     const float4 *vr = v + (size_t)(rv ? r0 + rr : 0) * 6 * V;
     for (int l0 = 0; l0 < Ns; l0 += 16) {
@@ -225,8 +262,9 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict_
             if (q < per) {
                 if (lv) a = pl[q];
                 if (rv) {
-                    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-                    b = vr[(long)c * V + p * Vh + bo + j];
+                    int c;
+                    const long site = dfl_site(boff, B, rb, Vbh, Vh, q, c);
+                    b = vr[(long)c * V + site];
                 }
             }
             // B operand per component: column (c, d) for which = 0, (d, -c) for which = 1
@@ -266,13 +304,12 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(const float4 *__restrict_
 // a fixed order.
 __global__ void __launch_bounds__(256) k_restrict_mfma64(const double2 *__restrict__ v, const float4 *__restrict__ phi,
                                                          const int *__restrict__ boff, double2 *__restrict__ u, long V,
-                                                         long Vh, int Vbh, int Ns, int Nb, int n) {
+                                                         long Vh, int Vbh, int rb, int Ns, int Nb, int n) {
     __shared__ double red[4][2][16][17];
     const int B = blockIdx.x, r0 = blockIdx.y * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, kk = lane >> 4;
-    const long per = 12L * Vbh;
-    const long bo = boff[B];
+    const long per = 12L * Vbh * rb;
     const bool rv = r0 + row < n;
     const double2 *vr = v + (size_t)(rv ? r0 + row : 0) * 12 * V;
     for (int l0 = 0; l0 < Ns; l0 += 16) {
@@ -286,8 +323,8 @@ __global__ void __launch_bounds__(256) k_restrict_mfma64(const double2 *__restri
             if (q < per) {
                 if (lv) a = pl[q];
                 if (rv) {
-                    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-                    const long site = p * Vh + bo + j;
+                    int c;
+                    const long site = dfl_site(boff, B, rb, Vbh, Vh, q, c);
                     b0 = vr[(long)(2 * c) * V + site];
                     b1 = vr[(long)(2 * c + 1) * V + site];
                 }
@@ -333,9 +370,10 @@ constexpr int PR = 12;
 template <class E, int MODE, bool STG>
 __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4 *__restrict__ phi,
                                                  const int *__restrict__ boff, const double2 *__restrict__ cf,
-                                                 long V, long Vh, int Vbh, int Ns, int Nb, int n, int nchunk) {
+                                                 long V, long Vh, int Vbh, int rb, int Ns, int Nb, int n,
+                                                 int nchunk) {
     const int B = blockIdx.x / nchunk;
-    const long per = 12L * Vbh;
+    const long per = 12L * Vbh * rb;
     const long q = (long)(blockIdx.x - B * nchunk) * 256 + threadIdx.x;
     const int r0 = blockIdx.y * PR;
     const int nr = min(PR, n - r0);
@@ -351,8 +389,8 @@ __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4
         __syncthreads();
     }
     if (q >= per) return;
-    const int c = (int)(q / (2 * Vbh)), p = (int)((q / Vbh) % 2), j = (int)(q % Vbh);
-    const long site = p * Vh + boff[B] + j;
+    int c;
+    const long site = dfl_site(boff, B, rb, Vbh, Vh, q, c);
     double ar[PR], ai[PR], br[PR], bi[PR];
 #pragma unroll
     for (int k = 0; k < PR; ++k) ar[k] = ai[k] = br[k] = bi[k] = 0;
@@ -523,18 +561,21 @@ __global__ void k_block_site_tables(Geom g, const int *__restrict__ lex_of, int 
     blex[idx] = Bl;
 }
 
-// canonical phi [Nb][Ns][Vb][12] complex128 <-> internal block storage
+// canonical phi [Nb][Ns][Vb][12] complex128 (Vb = 2 r Vbh sites of a
+// deflation block in local lexicographic order) <-> internal block storage
 __global__ void k_phi_export(const float4 *__restrict__ phi, double2 *__restrict__ out, const int *__restrict__ boff,
-                             const int *__restrict__ loc, long Vh, int Vbh, int Ns, int Nb) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over (B, l, p, j)
-    if (t >= (long)Nb * Ns * 2 * Vbh) return;
+                             const int *__restrict__ loc, long Vh, int Vbh, int r, int Ns, int Nb) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;  // over (B, l, m, p, j)
+    if (t >= (long)Nb * Ns * r * 2 * Vbh) return;
     const int j = (int)(t % Vbh), p = (int)((t / Vbh) % 2);
-    const long bl = t / (2 * Vbh);
+    const long q2 = t / (2 * Vbh);
+    const int m = (int)(q2 % r);
+    const long bl = q2 / r;
     const int l = (int)(bl % Ns), B = (int)(bl / Ns);
-    const long site = p * Vh + boff[B] + j;
+    const long site = p * Vh + boff[(long)B * r + m] + j;
     const int jl = loc[site];
-    const int Vb = 2 * Vbh;
-    const float4 *src = phi + ((size_t)B * Ns + l) * 12 * Vbh;
+    const long Vb = 2L * Vbh * r;
+    const float4 *src = phi + (((size_t)B * Ns + l) * r + m) * 12 * Vbh;
     double2 *dst = out + (((size_t)B * Ns + l) * Vb + jl) * 12;
     for (int c = 0; c < 6; ++c) {
         const float4 f = src[(size_t)c * 2 * Vbh + p * Vbh + j];
@@ -544,16 +585,18 @@ __global__ void k_phi_export(const float4 *__restrict__ phi, double2 *__restrict
 }
 
 __global__ void k_phi_import(const double2 *__restrict__ in, float4 *__restrict__ phi, const int *__restrict__ boff,
-                             const int *__restrict__ loc, long Vh, int Vbh, int Ns, int Nb) {
+                             const int *__restrict__ loc, long Vh, int Vbh, int r, int Ns, int Nb) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)Nb * Ns * 2 * Vbh) return;
+    if (t >= (long)Nb * Ns * r * 2 * Vbh) return;
     const int j = (int)(t % Vbh), p = (int)((t / Vbh) % 2);
-    const long bl = t / (2 * Vbh);
+    const long q2 = t / (2 * Vbh);
+    const int m = (int)(q2 % r);
+    const long bl = q2 / r;
     const int l = (int)(bl % Ns), B = (int)(bl / Ns);
-    const long site = p * Vh + boff[B] + j;
+    const long site = p * Vh + boff[(long)B * r + m] + j;
     const int jl = loc[site];
-    const int Vb = 2 * Vbh;
-    float4 *dst = phi + ((size_t)B * Ns + l) * 12 * Vbh;
+    const long Vb = 2L * Vbh * r;
+    float4 *dst = phi + (((size_t)B * Ns + l) * r + m) * 12 * Vbh;
     const double2 *src = in + (((size_t)B * Ns + l) * Vb + jl) * 12;
     for (int c = 0; c < 6; ++c) {
         const double2 a = src[2 * c], b = src[2 * c + 1];
@@ -601,10 +644,10 @@ int restrict_v(qcd_dfl d, const E *v, double2 *u, int n, hipStream_t s) {
     ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
     if constexpr (F32V)
         k_restrict_mfma<<<dim3(d->Nb, (n + 7) / 8), 256, 0, s>>>(reinterpret_cast<const float4 *>(v), d->phi, d->boff,
-                                                                  u, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n);
+                                                                  u, g.V, g.Vh, g.Vbh, d->r, d->Ns, d->Nb, n);
     else
-        k_restrict_mfma64<<<dim3(d->Nb, (n + 15) / 16), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->Ns,
-                                                                    d->Nb, n);
+        k_restrict_mfma64<<<dim3(d->Nb, (n + 15) / 16), 256, 0, s>>>(v, d->phi, d->boff, u, g.V, g.Vh, g.Vbh, d->r,
+                                                                    d->Ns, d->Nb, n);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -616,15 +659,15 @@ int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
     double fl, by;
     dfl_work_counts(d, n, (F32V ? 96 : 192) * (MODE == 0 ? 1 : 2), fl, by);
     ProfScope ps(PROF_DFL, s, fl, by, (double)g.V * n);
-    const int nchunk = (int)nblocks(12L * g.Vbh, 256);
+    const int nchunk = (int)nblocks(12L * g.Vbh * d->r, 256);
     const dim3 grid((unsigned)(d->Nb * nchunk), (n + PR - 1) / PR);
     const size_t stg = sizeof(double2) * (size_t)d->Ns * PR;
     if (stg <= 48 * 1024)
-        k_prolong<E, MODE, true><<<grid, 256, stg, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n,
-                                                        nchunk);
+        k_prolong<E, MODE, true><<<grid, 256, stg, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->r, d->Ns, d->Nb,
+                                                        n, nchunk);
     else
-        k_prolong<E, MODE, false><<<grid, 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->Ns, d->Nb, n,
-                                                       nchunk);
+        k_prolong<E, MODE, false><<<grid, 256, 0, s>>>(v, d->phi, d->boff, c, g.V, g.Vh, g.Vbh, d->r, d->Ns, d->Nb,
+                                                       n, nchunk);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -760,10 +803,10 @@ int build_little(qcd_dfl d, hipStream_t s) {
     for (int l = 0; l < Ns; ++l) {
         {
             ProfScope ps(PROF_DFL, s);
-            k_phi_field<<<nblocks((long)Nb * 12 * g.Vbh, 256), 256, 0, s>>>(d->phi, l, fl, d->boff, V, g.Vh, g.Vbh, Ns,
-                                                                            Nb);
-            k_dirac_split<<<nblocks(V, 128), 128, 0, s>>>(fl, out9, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, V, g.Vh,
-                                                          g.Vbh, f->lat.kappa);
+            k_phi_field<<<nblocks((long)Nb * 12 * g.Vbh * d->r, 256), 256, 0, s>>>(d->phi, l, fl, d->boff, V, g.Vh,
+                                                                                   g.Vbh, d->r, Ns, Nb);
+            k_dirac_split<<<nblocks(V, 128), 128, 0, s>>>(fl, out9, f->U[LNK_F64], f->clo[CLO_F64], f->nbr, d->dbof,
+                                                          V, g.Vh, g.Vbh, f->lat.kappa);
         }
         DFL_HIP(hipGetLastError());
         // u9[dd][B][k] = (phi_{B,k}, out_dd) ; treat the 9 outputs as 9 right-hand sides
@@ -788,12 +831,80 @@ void dfl_free(qcd_dfl d) {
     (void)hipFree(d->Dinv);
     (void)hipFree(d->bnbr);
     (void)hipFree(d->boff);
+    (void)hipFree(d->dbof);
     (void)hipFree(d->loc);
     (void)hipFree(d->blex);
     (void)hipDeviceSynchronize();
     ws_release(d->device, d->lw, d->lw_bytes);
     if (d->hp) (void)hipHostFree(d->hp);
     delete d;
+}
+
+// v_l <- v_l / ||v_l|| for Ns FP32 internal fields
+int normalise_fields(qcd_field f, float4 *v, int Ns, hipStream_t s) {
+    const long V = f->g.V;
+    void *sp;
+    DFL_TRY(field_buffer(f, BUF_RED, scalar_bytes(Ns), &sp));
+    Scal sc;
+    DFL_TRY(scalar_buffers_at(sp, Ns, sc));
+    DFL_TRY(blas_norm2<float4>(v, 6 * V, Ns, sc.part, sc.red, s));
+    k_normalise<<<dim3(nblocks(6 * V, 256), Ns), 256, 0, s>>>(v, 6 * V, sc.red);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+// the global fields restricted to the deflation blocks, orthonormalised per
+// block, and the little operator of that subspace
+int fields_to_subspace(qcd_dfl d, const float4 *v, hipStream_t s) {
+    qcd_field f = d->f;
+    const Geom &g = f->g;
+    const long per = 12L * g.Vbh * d->r;
+    const long tot = (long)d->Nb * d->Ns * per;
+    k_to_blocks<<<nblocks(tot, 256), 256, 0, s>>>(v, d->phi, d->boff, g.V, g.Vh, g.Vbh, d->r, d->Ns, d->Nb);
+    DFL_HIP(hipGetLastError());
+    DFL_HIP(hipMemsetAsync(f->flag, 0, sizeof(int), s));
+    k_block_mgs<<<d->Nb, 256, 0, s>>>(d->phi, d->Ns, per, f->flag);
+    DFL_HIP(hipGetLastError());
+    int flag = 0;
+    DFL_HIP(hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DFL_HIP(hipStreamSynchronize(s));
+    if (flag) return set_error(QCD_ESINGULAR, "deflation fields are linearly dependent on a block");
+    return build_little(d, s);
+}
+
+// one round v_l <- M^{-1} v_l / ||M^{-1} v_l|| for the Ns FP32 global
+// fields, each solve by the deflated SAP-GCR solver on the handle's current
+// subspace to relative residual params.ref_res (at most 256 iterations; a
+// solve stopped there still gives a valid inverse-iteration step), in
+// batches that fit the free device memory
+int inverse_iteration(qcd_dfl d, float4 *v, hipStream_t s) {
+    qcd_field f = d->f;
+    const long V = f->g.V;
+    const int Ns = d->Ns;
+    qcd_gcr q{};
+    q.nkv = 8;
+    q.nmx = 256;
+    q.fixed_iters = 0;
+    q.res = d->params.ref_res;
+    q.sap = d->params.sap;
+    q.dfl = d;
+    q.little_tol = 1e-8;
+    q.little_maxit = 16;
+    const int nb = std::max(1, std::min(Ns, pick_batch(f, q, 0)));
+    void *p;
+    DFL_TRY(field_buffer(f, BUF_APPLY, 2 * spinor_bytes(QCD_F64, V) * nb, &p));
+    double2 *b64 = static_cast<double2 *>(p), *x64 = b64 + (size_t)12 * V * nb;
+    for (int l0 = 0; l0 < Ns; l0 += nb) {
+        const int n = std::min(nb, Ns - l0);
+        float4 *vl = v + (size_t)6 * V * l0;
+        k_widen<<<dim3(nblocks(6 * V, 256), n), 256, 0, s>>>(vl, b64, V);
+        DFL_HIP(hipGetLastError());
+        const int rc = gcr_internal(f, &q, b64, x64, n, nullptr, s);
+        if (rc < 0) return rc;
+        k_narrow<<<dim3(nblocks(6 * V, 256), n), 256, 0, s>>>(x64, vl, V);
+        DFL_HIP(hipGetLastError());
+    }
+    return normalise_fields(f, v, Ns, s);
 }
 
 }  // namespace
@@ -837,60 +948,93 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     if (!f || !prm || !out) return set_error(QCD_EINVAL, "null argument to deflation_setup");
     *out = nullptr;
     const Geom &g = f->g;
-    if (prm->Ns < 1 || prm->Ns > 12 * g.Vb)
-        return set_error(QCD_ESINGULAR, "Ns must be between 1 and 12 times the block volume");
-    if (prm->ninv < 0) return set_error(QCD_EINVAL, "ninv must be >= 0");
+    // deflation blocks: the Schwarz block, or a multiple of it in every
+    // direction with an even number of blocks along each axis
+    Geom dg = g;
+    int rr[4];
+    for (int m = 0; m < 4; ++m) {
+        const int bd = prm->block[m] ? prm->block[m] : g.b[m];
+        if (bd < g.b[m] || bd % g.b[m] || g.L[m] % bd || (g.L[m] / bd) % 2)
+            return set_error(QCD_EGEOM, "the deflation block must be a multiple of the Schwarz block with an even "
+                                        "number of deflation blocks along every axis");
+        dg.b[m] = bd;
+        dg.nb[m] = g.L[m] / bd;
+        rr[m] = bd / g.b[m];
+    }
+    dg.Vb = dg.b[0] * dg.b[1] * dg.b[2] * dg.b[3];
+    dg.Vbh = dg.Vb / 2;
+    dg.Nb = (int)(g.V / dg.Vb);
+    if (prm->Ns < 1 || prm->Ns > 12 * dg.Vb)
+        return set_error(QCD_ESINGULAR, "Ns must be between 1 and 12 times the deflation block volume");
+    if (prm->ninv < 0 || prm->nref < 0) return set_error(QCD_EINVAL, "ninv and nref must be >= 0");
+    if (prm->nref > 0 && !(prm->ref_res > 0 && prm->ref_res < 1))
+        return set_error(QCD_EINVAL, "ref_res must be in (0, 1) when nref > 0");
     qcd_dfl d = new qcd_dfl_s();
     d->f = f;
     d->device = f->device;
     d->params = *prm;
     d->Ns = prm->Ns;
-    d->Nb = g.Nb;
+    d->Nb = dg.Nb;
+    d->dg = dg;
+    d->r = rr[0] * rr[1] * rr[2] * rr[3];
     auto fail = [&](int rc) {
         dfl_free(d);
         return rc;
     };
-    const int Ns = d->Ns, Nb = d->Nb;
+    const int Ns = d->Ns, Nb = d->Nb, r = d->r;
     const long V = g.V;
-    // block tables (lexicographic block order)
-    std::vector<int> boff(Nb), bnbr((size_t)Nb * 9), rank(Nb);
+    // Schwarz blocks: memory rank (colour-major) of each lexicographic block
+    std::vector<int> srank(g.Nb);
     {
         int cnt[2] = {0, 0};
-        for (int B = 0; B < Nb; ++B) {
-            int r = B, sum = 0;
+        for (int B = 0; B < g.Nb; ++B) {
+            int q = B, sum = 0;
             for (int m = 3; m >= 0; --m) {
-                sum += r % g.nb[m];
-                r /= g.nb[m];
+                sum += q % g.nb[m];
+                q /= g.nb[m];
             }
-            rank[B] = (sum & 1) * (Nb / 2) + cnt[sum & 1]++;
-            boff[B] = rank[B] * g.Vbh;
+            srank[B] = (sum & 1) * (g.Nb / 2) + cnt[sum & 1]++;
         }
-        for (int B = 0; B < Nb; ++B) {
-            int c[4], r = B;
+    }
+    // deflation-block tables (lexicographic order of the deflation-block grid)
+    std::vector<int> boff((size_t)Nb * r), dbof(g.Nb), bnbr((size_t)Nb * 9);
+    for (int B = 0; B < Nb; ++B) {
+        int c[4], q = B;
+        for (int m = 3; m >= 0; --m) {
+            c[m] = q % dg.nb[m];
+            q /= dg.nb[m];
+        }
+        for (int k = 0; k < r; ++k) {   // member k: lexicographic inside the deflation block
+            int sc[4], t = k;
             for (int m = 3; m >= 0; --m) {
-                c[m] = r % g.nb[m];
-                r /= g.nb[m];
+                sc[m] = c[m] * rr[m] + t % rr[m];
+                t /= rr[m];
             }
-            bnbr[(size_t)B * 9] = B;
-            for (int mu = 0; mu < 4; ++mu)
-                for (int dir = 0; dir < 2; ++dir) {
-                    int cc[4] = {c[0], c[1], c[2], c[3]};
-                    cc[mu] = (cc[mu] + (dir == 0 ? 1 : -1) + g.nb[mu]) % g.nb[mu];
-                    int k = 0;
-                    for (int m = 0; m < 4; ++m) k = k * g.nb[m] + cc[m];
-                    bnbr[(size_t)B * 9 + 1 + 2 * mu + dir] = k;
-                }
+            int Bs = 0;
+            for (int m = 0; m < 4; ++m) Bs = Bs * g.nb[m] + sc[m];
+            boff[(size_t)B * r + k] = srank[Bs] * g.Vbh;
+            dbof[srank[Bs]] = B;
         }
+        bnbr[(size_t)B * 9] = B;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int dir = 0; dir < 2; ++dir) {
+                int cc[4] = {c[0], c[1], c[2], c[3]};
+                cc[mu] = (cc[mu] + (dir == 0 ? 1 : -1) + dg.nb[mu]) % dg.nb[mu];
+                int k = 0;
+                for (int m = 0; m < 4; ++m) k = k * dg.nb[m] + cc[m];
+                bnbr[(size_t)B * 9 + 1 + 2 * mu + dir] = k;
+            }
     }
 #define DALLOC(ptr, bytes)                                                                 \
     if (!dev_alloc(d->device, (void **)&(ptr), (bytes))) {                                \
         return fail(set_error(QCD_ENOMEM, "device allocation failed in deflation_setup")); \
     }
-    DALLOC(d->phi, sizeof(float4) * (size_t)Nb * Ns * 12 * g.Vbh);
+    DALLOC(d->phi, sizeof(float4) * (size_t)Nb * Ns * 12 * r * g.Vbh);
     DALLOC(d->A, sizeof(double2) * (size_t)Nb * 9 * Ns * Ns);
     DALLOC(d->Dinv, sizeof(double2) * (size_t)Nb * Ns * Ns);
     DALLOC(d->bnbr, sizeof(int) * (size_t)Nb * 9);
-    DALLOC(d->boff, sizeof(int) * Nb);
+    DALLOC(d->boff, sizeof(int) * (size_t)Nb * r);
+    DALLOC(d->dbof, sizeof(int) * (size_t)g.Nb);
     DALLOC(d->loc, sizeof(int) * V);
     DALLOC(d->blex, sizeof(int) * V);
 #undef DALLOC
@@ -899,9 +1043,10 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
         return fail(set_error(QCD_ENOMEM, "pinned host allocation failed"));
     }
     hipError_t e = hipMemcpyAsync(d->bnbr, bnbr.data(), sizeof(int) * bnbr.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d->boff, boff.data(), sizeof(int) * Nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->boff, boff.data(), sizeof(int) * boff.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->dbof, dbof.data(), sizeof(int) * dbof.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        k_block_site_tables<<<nblocks(V, 256), 256, 0, s>>>(g, f->lex_of, d->loc, d->blex);
+        k_block_site_tables<<<nblocks(V, 256), 256, 0, s>>>(dg, f->lex_of, d->loc, d->blex);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -915,34 +1060,25 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     const unsigned long long key = sm64(prm->seed, 5ULL);   // stream 5: deflation fields
     k_random_fields<<<dim3(nblocks(V, 256), Ns), 256, 0, s>>>(v, key, f->lex_of, V);
     if ((e = hipGetLastError()) != hipSuccess) return fail(set_error(QCD_EHIP, hipGetErrorString(e)));
-    void *sp;
-    rc = field_buffer(f, BUF_RED, scalar_bytes(Ns), &sp);
-    if (rc < 0) return fail(rc);
-    Scal sc;
-    scalar_buffers_at(sp, Ns, sc);
     qcd_sap sap = prm->sap;
     if (sap.storage == QCD_F64) sap.storage = QCD_F32;   // the fields are refined in FP32
     for (int it = 0; it < prm->ninv; ++it) {
         rc = sap_internal(f, &sap, v, w, Ns, s);
         if (rc < 0) return fail(rc);
         std::swap(v, w);
-        rc = blas_norm2<float4>(v, 6 * V, Ns, sc.part, sc.red, s);
+        rc = normalise_fields(f, v, Ns, s);
         if (rc < 0) return fail(rc);
-        k_normalise<<<dim3(nblocks(6 * V, 256), Ns), 256, 0, s>>>(v, 6 * V, sc.red);
     }
-    {
-        const long tot = (long)Nb * Ns * 12 * g.Vbh;
-        k_to_blocks<<<nblocks(tot, 256), 256, 0, s>>>(v, d->phi, d->boff, V, g.Vh, g.Vbh, Ns, Nb);
-        (void)hipMemsetAsync(f->flag, 0, sizeof(int), s);
-        k_block_mgs<<<Nb, 256, 0, s>>>(d->phi, Ns, g.Vbh, f->flag);
-        int flag = 0;
-        e = hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("deflation fields: ") + hipGetErrorString(e)));
-        if (flag) return fail(set_error(QCD_ESINGULAR, "deflation fields are linearly dependent on a block"));
-    }
-    rc = build_little(d, s);
+    rc = fields_to_subspace(d, v, s);
     if (rc < 0) return fail(rc);
+    // refinement: inverse iteration v <- M^{-1} v / ||.|| with the deflated
+    // solver on the current subspace, a new subspace after every round
+    for (int it = 0; it < prm->nref; ++it) {
+        rc = inverse_iteration(d, v, s);
+        if (rc < 0) return fail(rc);
+        rc = fields_to_subspace(d, v, s);
+        if (rc < 0) return fail(rc);
+    }
     *out = d;
     return 0;
 }
@@ -962,9 +1098,9 @@ int deflation_dims(qcd_dfl d, int *Nb, int *Ns) {
 int deflation_get_phi(qcd_dfl d, void *phi, hipStream_t s) {
     if (!d || !phi) return set_error(QCD_EINVAL, "null argument to deflation_get_phi");
     const Geom &g = d->f->g;
-    const long tot = (long)d->Nb * d->Ns * 2 * g.Vbh;
+    const long tot = (long)d->Nb * d->Ns * d->r * 2 * g.Vbh;
     k_phi_export<<<nblocks(tot, 256), 256, 0, s>>>(d->phi, static_cast<double2 *>(phi), d->boff, d->loc, g.Vh, g.Vbh,
-                                                   d->Ns, d->Nb);
+                                                   d->r, d->Ns, d->Nb);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -972,9 +1108,9 @@ int deflation_get_phi(qcd_dfl d, void *phi, hipStream_t s) {
 int deflation_set_phi(qcd_dfl d, const void *phi, hipStream_t s) {
     if (!d || !phi) return set_error(QCD_EINVAL, "null argument to deflation_set_phi");
     const Geom &g = d->f->g;
-    const long tot = (long)d->Nb * d->Ns * 2 * g.Vbh;
+    const long tot = (long)d->Nb * d->Ns * d->r * 2 * g.Vbh;
     k_phi_import<<<nblocks(tot, 256), 256, 0, s>>>(static_cast<const double2 *>(phi), d->phi, d->boff, d->loc, g.Vh,
-                                                   g.Vbh, d->Ns, d->Nb);
+                                                   g.Vbh, d->r, d->Ns, d->Nb);
     DFL_HIP(hipGetLastError());
     return build_little(d, s);
 }

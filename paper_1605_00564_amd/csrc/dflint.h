@@ -6,16 +6,20 @@ struct qcd_dfl_s {
     qcd_field f = nullptr;
     int device = 0;
     qcd_dfl_params params{};
-    int Ns = 0, Nb = 0;
-    // Phi: [Nb][Ns][6 chunks][2 parities][Vbh] float4, blocks in lexicographic
-    // order of the block grid, sites of a block in the internal (parity, j) order
+    int Ns = 0, Nb = 0;        // Nb: deflation blocks
+    int r = 1;                 // Schwarz blocks per deflation block
+    dfl::Geom dg{};            // deflation-block geometry (b = deflation block, nb its grid)
+    // Phi: [Nb][Ns][r members][6 chunks][2 parities][Vbh] float4: deflation
+    // blocks in lexicographic order of their grid, member Schwarz blocks in
+    // lexicographic order inside, sites of a member in the internal (parity, j) order
     float4 *phi = nullptr;
     double2 *A = nullptr;      // little operator [Nb][9][Ns][Ns], d = 0 self, 1+2mu+dir neighbours
     double2 *Dinv = nullptr;   // inverse diagonal blocks [Nb][Ns][Ns]
-    int *bnbr = nullptr;       // [Nb][9] neighbour block (lexicographic), d as for A
-    int *boff = nullptr;       // [Nb] internal site offset B_int * Vbh of lexicographic block B
-    int *loc = nullptr;        // [V] internal site -> lexicographic site index inside its block
-    int *blex = nullptr;       // [V] internal site -> lexicographic block index
+    int *bnbr = nullptr;       // [Nb][9] neighbour deflation block (lexicographic), d as for A
+    int *boff = nullptr;       // [Nb][r] internal site offset (rank * Vbh) of each member Schwarz block
+    int *dbof = nullptr;       // [Schwarz blocks] deflation block of the Schwarz block of memory rank k
+    int *loc = nullptr;        // [V] internal site -> lexicographic site index inside its deflation block
+    int *blex = nullptr;       // [V] internal site -> lexicographic deflation block index
     // grow-only work space for little-vector algebra
     void *lw = nullptr;
     size_t lw_bytes = 0;
