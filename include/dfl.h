@@ -275,7 +275,7 @@ typedef struct {
     qcd_gcr sloppy, exact_params;
     qcd_prec sloppy_out;           /* QCD_F64 or QCD_F32 */
     int batch;                     /* right-hand sides per solver launch (0: library choice); lowered
-                                      to what 60% of the free device memory holds */
+                                      (to an even count) only if 90% of the free memory cannot hold it */
 } qcd_ama;
 
 int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const *x_exact, qcd_prec io,

@@ -24,24 +24,31 @@ __global__ void k_point_sources(double2 *__restrict__ b, const int *__restrict__
     b[((size_t)slot * 12 + sc) * V + int_of[lex]] = make_double2(1.0, 0.0);
 }
 
-// right-hand sides per launch: as many as 60% of the free device memory
-// (plus the library's cached workspace) holds for these parameters, at most
-// 48 and a multiple of 12 when possible; a caller's request is lowered to
-// that bound (memory only: per right-hand side the results do not depend
-// on the batch)
+// right-hand sides per launch.  Without a request (want = 0): as many as
+// 60% of the available device memory holds for these parameters, at most 48
+// and a multiple of 12 when possible.  A request is lowered only when 90% of
+// the available memory cannot hold it, and then to an even count (the
+// Schwarz and stencil kernels take right-hand sides in pairs).  Available:
+// free device memory, the library's cached workspace and the handle's own
+// buffers.  Memory only: per right-hand side the results do not depend on
+// the batch.
 int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
         (void)hipGetLastError();
         return want > 0 ? want : 12;
     }
-    freeb += ws_cached_bytes(f->device);   // cached workspace is reusable
+    freeb += ws_cached_bytes(f->device);
+    for (size_t k = 0; k < sizeof(f->buf_bytes) / sizeof(f->buf_bytes[0]); ++k) freeb += f->buf_bytes[k];
     const size_t V = f->g.V;
     const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
-    const size_t per = V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5);
-    const size_t fit = std::max<size_t>((size_t)(0.6 * (double)freeb) / std::max<size_t>(per, 1), 1);
-    if (want > 0) return (int)std::min<size_t>((size_t)want, fit);
-    size_t n = std::min<size_t>(fit, 48);
+    const size_t per = std::max<size_t>(V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5), 1);
+    if (want > 0) {
+        const size_t fit = (size_t)(0.9 * (double)freeb) / per;
+        if ((size_t)want <= fit) return want;
+        return (int)std::max<size_t>(fit - fit % 2, 1);
+    }
+    size_t n = std::min<size_t>(std::max<size_t>((size_t)(0.6 * (double)freeb) / per, 1), 48);
     if (n >= 12) n -= n % 12;
     return (int)n;
 }

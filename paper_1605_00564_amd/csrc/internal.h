@@ -696,9 +696,9 @@ int gcr_internal(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, in
 // replayed from a HIP graph captured on the first call with this batch size,
 // parameters and workspace vectors; status becomes QCD_NOCONV if any
 // solution misses p.res
-// right-hand sides per solver launch for parameters p: want (> 0) lowered to
-// what 60% of the free device memory holds, or (want = 0) that bound, at most
-// 48 and a multiple of 12 when possible
+// right-hand sides per solver launch for parameters p: want (> 0), lowered
+// to an even count only if 90% of the available memory cannot hold it, or
+// (want = 0) what 60% of it holds, at most 48 and a multiple of 12 when possible
 int pick_batch(qcd_field f, const qcd_gcr &p, int want);
 int solve_batch(qcd_field f, const qcd_gcr &p, const double2 *b64, double2 *x64, int n, bool graph, qcd_info *info,
                 hipStream_t s, int &status);
