@@ -458,7 +458,8 @@ MULTI_FIELDS = [((48, 24, 24, 24), 1, 8), ((64, 32, 32, 32), 2, 32), ((96, 48, 4
 def run_multi(args, log):
     """Three gauge fields with 8, 32 and 64 sources: half of them Z2 noise
     vectors built on the device, the other half point sources (whole
-    positions of 12 spin-colours, so 1, 2 and 3 positions); the first
+    positions of 12 spin-colours, so 1, 2 and 3 positions, two Schwarz
+    blocks apart along t so that the set stays covariant); the first
     position of each field is also solved exactly (1e-10).  Per field the
     autotuner picks the Schwarz/deflation block shape, the right-hand sides
     per launch, the outer iteration count N_iter and the stencil variant
@@ -494,9 +495,11 @@ def run_multi(args, log):
         sloppy = tune.sloppy_params(d, choice.fixed_iters)
         exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=dfl.SapParams(5, 4, F32), dfl=d, little_tol=1e-10,
                               little_maxit=16)
+        # positions of one set differ by shifts that map the Schwarz block
+        # checkerboard onto itself: two blocks along t per position
         npts = -(-(nsrc // 2) // 12)
-        pts = [tuple(int(v) for v in synth.coords(dims, synth.seeded_site(dims, 1000 * seed + k)))
-               for k in range(npts)]
+        x0 = tuple(int(v) for v in synth.coords(dims, synth.seeded_site(dims, 1000 * seed)))
+        pts = [((x0[0] + 2 * choice.block[0] * k) % dims[0],) + x0[1:] for k in range(npts)]
         srcs = [dfl.z2(seed=seed, index=0, nvec=nsrc // 2)] + [dfl.point(p) for p in pts]
         fields.append((fld, d))
         sets.append(dict(sources=srcs, exact_flags=[False, True] + [False] * (npts - 1), sloppy=sloppy, exact=exact,

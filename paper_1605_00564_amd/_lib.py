@@ -15,6 +15,8 @@ import numpy as np
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 SRC_POINT, SRC_Z2, SRC_SEQ, SRC_VEC = 0, 1, 2, 3
+# return codes (include/dfl.h)
+QCD_NOCONV, QCD_EINVAL, QCD_EGEOM, QCD_ENOMEM, QCD_EHIP, QCD_ESINGULAR, QCD_ENAN, QCD_ENOTSET = 1, -1, -2, -3, -4, -5, -6, -7
 NOCONV = 1
 PROF_CLASSES = ("dirac", "sap", "deflation", "little", "blas", "other")
 

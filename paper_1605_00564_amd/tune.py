@@ -170,24 +170,36 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
         # untimed: free the previous candidate's scratch, so that every
         # candidate's setup makes the same allocations
         L.workspace_trim()
-        t0 = time.perf_counter()
-        fld = L.Field(dims, b, kappa, csw, U)
-        d = L.Deflation(fld, Ns=Ns, ninv=ninv, seed=7, sap=sap)
-        _sync()
-        setup = time.perf_counter() - t0
-        if nb is None:
-            # one trial batch size for every shape, so that they compare fairly
+        fld = d = None
+        try:
+            t0 = time.perf_counter()
+            fld = L.Field(dims, b, kappa, csw, U)
+            d = L.Deflation(fld, Ns=Ns, ninv=ninv, seed=7, sap=sap)
+            _sync()
+            setup = time.perf_counter() - t0
+            if nb is None:
+                # one trial batch size for every shape, so that they compare fairly
+                fld.trim()
+                nb = max(1, min(nsrc, memory_batch_limit(V, fixed_iters + 2), batches[0]))
+            srcs = list(L.z2_sources(fld, seed=99, n=nb))
+            iters = fixed_iters
+            while True:
+                per, worst = _trial(fld, d, srcs, nb, iters, res)
+                if worst <= margin * res or iters >= max_iters:
+                    break
+                iters += 1
+            del srcs
             fld.trim()
-            nb = max(1, min(nsrc, memory_batch_limit(V, fixed_iters + 2), batches[0]))
-        srcs = list(L.z2_sources(fld, seed=99, n=nb))
-        iters = fixed_iters
-        while True:
-            per, worst = _trial(fld, d, srcs, nb, iters, res)
-            if worst <= margin * res or iters >= max_iters:
-                break
-            iters += 1
-        del srcs
-        fld.trim()
+        except L.DflError as e:
+            # a shape whose buffers do not fit beside the handles already held
+            # (the best candidate so far, other fields' handles) is no choice
+            if e.code != L.QCD_ENOMEM or best is None:
+                raise
+            log(f"[tune] block {b}: skipped, out of device memory ({e})")
+            for h in (d, fld):
+                if h is not None:
+                    h.close()
+            continue
         cost = nsrc * per
         table.append({"block": b, "batch": nb, "fixed_iters": iters, "setup_s": setup, "per_source_s": per,
                       "trial_rel_res": worst, "solve_cost_s": cost, "volume": V})
