@@ -73,88 +73,118 @@ __device__ inline void block_sum(double (&v)[NV], double (*sh)[NV]) {
         for (int k = 0; k < NV; ++k) v[k] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
 }
 
-// Two-point contraction of the sites of timeslice blockIdx.y, chunk
-// blockIdx.x of 256 spatial sites; partial sums part[t][chunk][16] (complex)
+// Two-point contraction: a workgroup takes SPW2 = 8 consecutive sites of
+// timeslice blockIdx.y (chunk blockIdx.x), 16 threads per site.  The sites'
+// propagators are staged in LDS (one 12 x 12 complex matrix per site,
+// S[s c][s' c']), and the colour sums are factored:
+//   T^{cc'}        = eps_abc eps_a'b'c' tr(Q^{bb'} S^{aa' T})         (9 per site)
+//   Y^{ca'}_{r al'} = eps_abc eps_a'b'c' sum_s Q^{bb'}_{s r} S^{ac'}_{s al'}   (9 x 16)
+//   C_{al al'}     = sum_cc' T^{cc'} S^{cc'}_{al al'} - sum_{c a' r} S^{ca'}_{al r} Y^{ca'}_{r al'}
+// with Q^{bb'}_{s r} = g_s g_{q} S_{pi(s) b, q b'}, q = pi^-1(r).  Thread
+// l = 0..15 of a site computes T^{cc'} (l < 9), then Y for (r, al') =
+// (l / 4, l % 4), then C for (al, al') = (l / 4, l % 4).  The 16 sites'
+// values are summed in a fixed order into part[t][chunk][16].  LDS: 40 KB
+// per workgroup of 128 threads.
+constexpr int SPW2 = 8;
+// Q^{bb'}_{s r} = coef[4 s + r] S_{row[4 s + r] b, col[4 s + r] b'} (built on
+// the host from Gamma; the unrolled loops read it from kernel arguments)
+struct QMap {
+    double re[16], im[16];
+    int row[16], col[16];
+};
 template <class CT>
-__global__ void __launch_bounds__(256) k_nucleon_2pt(const CT *__restrict__ prop, long V, long spatial,
-                                                     Mono4 G, double2 *__restrict__ part) {
-    __shared__ double sh[4][32];
-    const long loc = (long)blockIdx.x * 256 + threadIdx.x;
-    const bool on = loc < spatial;
-    double acc[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) acc[k] = 0.0;
-    if (on) {
-        const Prop<CT> S{prop, V, (unsigned long long)((long)blockIdx.y * spatial + loc)};
-        cd C[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) C[i][j] = {0.0, 0.0};
-        for (int b = 0; b < 3; ++b)
-            for (int bp = 0; bp < 3; ++bp) {
-                cd Q[4][4];
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int sp = 0; sp < 4; ++sp) {
-                        const int q = G.pinv[sp];
-                        Q[s][sp] = (mono_g(G, s) * mono_g(G, q)) * S(G.pi[s], b, q, bp);
-                    }
-                int a0, c0, a1, c1;
-                others(b, a0, c0);
-                others(bp, a1, c1);
-                for (int o = 0; o < 2; ++o)
-                    for (int op = 0; op < 2; ++op) {
-                        // (a, c) = (a0, c0) has eps(a, b, c) = -1, the swap +1
-                        const int a = o ? c0 : a0, c = o ? a0 : c0;
-                        const int ap = op ? c1 : a1, cp = op ? a1 : c1;
-                        const double sg = (o == op) ? 1.0 : -1.0;
-                        // term 1: C += eps eps tr(Q^{bb'} S^{aa' T}) S^{cc'}
-                        cd tr = {0.0, 0.0};
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-#pragma unroll
-                            for (int sp = 0; sp < 4; ++sp) tr = cmac(tr, Q[s][sp], S(s, a, sp, ap));
-                        tr = sg * tr;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) C[i][j] = cmac(C[i][j], tr, S(i, c, j, cp));
-                        // term 2: C -= eps eps S^{ca'} Q^T S^{ac'}
-#pragma unroll
-                        for (int al = 0; al < 4; ++al) {
-                            cd X[4];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                cd x = {0.0, 0.0};
-#pragma unroll
-                                for (int s = 0; s < 4; ++s) x = cmac(x, Q[s][r], S(s, a, al, cp));
-                                X[r] = x;
-                            }
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                cd y = {0.0, 0.0};
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) y = cmac(y, S(i, c, r, ap), X[r]);
-                                C[i][al] = rmac(C[i][al], -sg, y);
-                            }
-                        }
-                    }
-            }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[2 * (4 * i + j)] = C[i][j].re;
-                acc[2 * (4 * i + j) + 1] = C[i][j].im;
-            }
+__global__ void __launch_bounds__(16 * SPW2) k_nucleon_2pt(const CT *__restrict__ prop, long V, long spatial,
+                                                           QMap M, double2 *__restrict__ part) {
+    __shared__ cd Sh[SPW2][144];
+    __shared__ cd Th[SPW2][9];
+    __shared__ cd Yh[SPW2][9][16];
+    __shared__ cd Ch[SPW2][16];
+    const long base = (long)blockIdx.x * SPW2;          // first spatial site of the workgroup
+    const long x0 = (long)blockIdx.y * spatial + base;  // its lexicographic index
+    const int nsite = (int)min((long)SPW2, spatial - base);
+    // stage: for vector j the workgroup's sites are 12 nsite consecutive complex numbers
+    for (int e = threadIdx.x; e < 12 * 12 * SPW2; e += 16 * SPW2) {
+        const int j = e / (12 * SPW2), rem = e - j * 12 * SPW2;
+        const int site = rem / 12, k = rem - site * 12;
+        cd v = {0.0, 0.0};
+        if (site < nsite) {
+            const CT t = prop[((size_t)j * V + x0 + site) * 12 + k];
+            v = {(double)t.x, (double)t.y};
+        }
+        Sh[site][k * 12 + j] = v;
     }
-    block_sum<32>(acc, sh);
-    if (threadIdx.x == 0) {
-        double2 *o = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 16;
+    __syncthreads();
+    const int site = threadIdx.x >> 4, l = threadIdx.x & 15;
+    const cd *S = Sh[site];
+    // eps_abc for the two (a, b) of a given c: (c+1, c+2) -> +1, (c+2, c+1) -> -1
+    if (l < 9) {
+        const int c = l / 3, cp = l % 3;
+        cd T = {0.0, 0.0};
+#pragma unroll 1
+        for (int o = 0; o < 4; ++o) {
+            const int a = (o & 2) ? (c + 2) % 3 : (c + 1) % 3, b = (o & 2) ? (c + 1) % 3 : (c + 2) % 3;
+            const int ap = (o & 1) ? (cp + 2) % 3 : (cp + 1) % 3, bp = (o & 1) ? (cp + 1) % 3 : (cp + 2) % 3;
+            const cd *Sb = S + b * 12 + bp, *Sa = S + a * 12 + ap;
+            cd tr = {0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 16; ++k) o[k] = make_double2(acc[2 * k], acc[2 * k + 1]);
+            for (int sr = 0; sr < 16; ++sr) {
+                const cd Q = cd{M.re[sr], M.im[sr]} * Sb[36 * M.row[sr] + 3 * M.col[sr]];
+                tr = cmac(tr, Q, Sa[36 * (sr >> 2) + 3 * (sr & 3)]);
+            }
+            T = (o == 0 || o == 3) ? T + tr : T - tr;
+        }
+        Th[site][l] = T;
+    }
+    {
+        const int r = l >> 2, alp = l & 3;
+#pragma unroll 1
+        for (int cap = 0; cap < 9; ++cap) {
+            const int c = cap / 3, ap = cap - 3 * c;
+            cd Y = {0.0, 0.0};
+#pragma unroll 1
+            for (int o = 0; o < 4; ++o) {
+                const int a = (o & 2) ? (c + 2) % 3 : (c + 1) % 3, b = (o & 2) ? (c + 1) % 3 : (c + 2) % 3;
+                // (b', c') with eps_a'b'c': (a'+1, a'+2) -> +1, (a'+2, a'+1) -> -1
+                const int bp = (o & 1) ? (ap + 2) % 3 : (ap + 1) % 3, cp = (o & 1) ? (ap + 1) % 3 : (ap + 2) % 3;
+                const cd *Sb = S + b * 12 + bp, *Sa = S + a * 12 + 3 * alp + cp;
+                cd y = {0.0, 0.0};
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    // Q_{s r} for this thread's r: one of the 16 map entries per s
+                    const int sr = 4 * s4;
+                    cd Q = {0.0, 0.0};
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        if (rr == r) Q = cd{M.re[sr + rr], M.im[sr + rr]} * Sb[36 * M.row[sr + rr] + 3 * M.col[sr + rr]];
+                    y = cmac(y, Q, Sa[36 * s4]);
+                }
+                Y = (o == 0 || o == 3) ? Y + y : Y - y;
+            }
+            Yh[site][cap][l] = Y;
+        }
+    }
+    __syncthreads();
+    {
+        const int al = l >> 2, alp = l & 3;
+        const cd *Sl = S + 36 * al;
+        cd C = {0.0, 0.0};
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int cp = 0; cp < 3; ++cp) C = cmac(C, Th[site][3 * c + cp], Sl[c * 12 + 3 * alp + cp]);
+#pragma unroll 1
+        for (int cap = 0; cap < 9; ++cap) {
+            const int c = cap / 3, ap = cap - 3 * c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) C = C - Sl[c * 12 + 3 * r + ap] * Yh[site][cap][4 * r + alp];
+        }
+        Ch[site][l] = site < nsite ? C : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        cd sum = {0.0, 0.0};
+        for (int k = 0; k < SPW2; ++k) sum = sum + Ch[k][threadIdx.x];
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 16 + threadIdx.x] = make_double2(sum.re, sum.im);
     }
 }
 
@@ -444,10 +474,11 @@ int check_prop_args(qcd_field f, const void *a, const void *b, qcd_prec io) {
     return 0;
 }
 
-// per-chunk partial sums of a timeslice reduction, nk complex values each
-int partials(qcd_field f, int nk, unsigned &nchunk, double2 **part) {
+// per-chunk partial sums of a timeslice reduction, nk complex values each,
+// chunks of `per` spatial sites
+int partials(qcd_field f, int nk, unsigned &nchunk, double2 **part, long per = 256) {
     const long spatial = f->g.V / f->g.L[0];
-    nchunk = nblocks(spatial, 256);
+    nchunk = nblocks(spatial, per);
     void *p;
     DFL_TRY(field_buffer(f, BUF_CONTRACT, sizeof(double2) * (size_t)f->g.L[0] * nchunk * nk, &p));
     *part = static_cast<double2 *>(p);
@@ -466,15 +497,28 @@ extern "C" int nucleon_2pt(qcd_field f, const void *prop, qcd_prec io, int t0, v
     const long V = f->g.V, spatial = V / T;
     unsigned nchunk;
     double2 *part;
-    DFL_TRY(partials(f, 16, nchunk, &part));
+    DFL_TRY(partials(f, 16, nchunk, &part, SPW2));
     const Mono4 G = cg5_mono();
+    QMap QM;
+    for (int s4 = 0; s4 < 4; ++s4)
+        for (int r = 0; r < 4; ++r) {
+            const int q = G.pinv[r];
+            const std::complex<double> g = std::complex<double>(G.gre[s4], G.gim[s4]) *
+                                           std::complex<double>(G.gre[q], G.gim[q]);
+            QM.re[4 * s4 + r] = g.real();
+            QM.im[4 * s4 + r] = g.imag();
+            QM.row[4 * s4 + r] = G.pi[s4];
+            QM.col[4 * s4 + r] = q;
+        }
     {
         ProfScope ps(PROF_OTHER, s);
         const dim3 grid(nchunk, T);
         if (io == QCD_F64)
-            k_nucleon_2pt<double2><<<grid, 256, 0, s>>>(static_cast<const double2 *>(prop), V, spatial, G, part);
+            k_nucleon_2pt<double2><<<grid, 16 * SPW2, 0, s>>>(static_cast<const double2 *>(prop), V, spatial, QM,
+                                                               part);
         else
-            k_nucleon_2pt<float2><<<grid, 256, 0, s>>>(static_cast<const float2 *>(prop), V, spatial, G, part);
+            k_nucleon_2pt<float2><<<grid, 16 * SPW2, 0, s>>>(static_cast<const float2 *>(prop), V, spatial, QM,
+                                                              part);
         DFL_HIP(hipGetLastError());
         k_timeslice_reduce<<<nblocks(16L * T, 64), 64, 0, s>>>(part, nchunk, T, 16, t0, static_cast<double2 *>(corr));
         DFL_HIP(hipGetLastError());
