@@ -174,3 +174,49 @@ def test_invalid_deflation_blocks_are_rejected(dblock):
     with pytest.raises(dfl.DflError) as e:
         dfl.Deflation(fld, Ns=4, ninv=0, block=dblock)
     assert e.value.code == -2
+
+
+def test_graph_replay_and_multi_field_with_deflation_blocks():
+    """Fixed-iteration batched solves with 4^4 deflation blocks over 2^4
+    Schwarz blocks, replayed from captured graphs: a replay returns the
+    captured call's bits, and the reported residuals of the graph and the
+    eager solves are the oracle's (the two differ in the low-mode
+    correction's little solve: polled to its tolerance eagerly, one fixed
+    cycle in a graph); an
+    ama_solve_multi call over this field and a second field with tied 4^4
+    blocks equals one ama_solve per field."""
+    torch, dfl = _gpu()
+    op, fld = field()
+    sap = dfl.SapParams(5, 4, F32)
+    d = dfl.Deflation(fld, Ns=6, ninv=2, seed=51, sap=sap, block=(4, 4, 4, 4))
+    p = dfl.GcrParams(nkv=4, fixed_iters=3, res=3e-3, sap=sap, dfl=d, little_tol=1e-6, little_maxit=4)
+    b = [torch.from_numpy(v).cuda() for v in synth.gaussian_spinor(DIMS, 6, 2301)]
+    xg, ig = dfl.gcr_solve_batched(fld, b, p, batch=3, graph=True)
+    xg2, ig2 = dfl.gcr_solve_batched(fld, b, p, batch=3, graph=True)
+    xe, ie = dfl.gcr_solve_batched(fld, b, p, batch=3, graph=False)
+    for r in range(6):
+        assert torch.equal(xg[r], xg2[r]), r
+        bb = b[r].cpu().numpy()
+        for x, i in ((xg[r], ig[r]), (xe[r], ie[r])):
+            rr = oracle.norm(bb - op.M(x.cpu().numpy())) / oracle.norm(bb)
+            assert abs(i.rel_res - rr) <= 1e-9 * rr, (r, i.rel_res, rr)
+        print("replayed / eager residual", ig[r].rel_res, ie[r].rel_res)
+    dims2 = (8, 8, 8, 8)
+    U2 = synth.gauge_field(dims2, 0.3, 4)
+    f2 = dfl.Field(dims2, (4, 4, 4, 4), KAPPA, CSW, U2)
+    d2 = dfl.Deflation(f2, Ns=6, ninv=2, seed=52, sap=sap)
+    sl = lambda dd: dfl.GcrParams(nkv=8, nmx=30, res=3e-3, sap=sap, dfl=dd, little_tol=1e-6, little_maxit=4)
+    ex = lambda dd: dfl.GcrParams(nkv=16, nmx=300, res=1e-10, sap=sap, dfl=dd, little_tol=1e-10, little_maxit=16)
+    sets = [dict(sources=[dfl.point((1, 2, 3, 0)), dfl.z2(seed=3, nvec=2)], exact_flags=[True, False],
+                 sloppy=sl(d), exact=ex(d), batch=12),
+            dict(sources=[dfl.z2(seed=4, nvec=3)], exact_flags=[True], sloppy=sl(d2), exact=ex(d2), batch=12)]
+    got = dfl.ama_solve_multi([fld, f2], sets, dtype=torch.complex128)
+    for (fh, st), g in zip(((fld, sets[0]), (f2, sets[1])), got):
+        ref = dfl.ama_solve(fh, st["sources"], st["exact_flags"], st["sloppy"], st["exact"],
+                            dtype=torch.complex128, batch=12)
+        for a, c in zip(g[0] + g[1], ref[0] + ref[1]):
+            assert torch.equal(a, c)
+        assert all(i.status == 0 for i in g[2] + g[3])
+    d2.close()
+    f2.close()
+    d.close()

@@ -55,7 +55,7 @@ def test_two_point_contraction_matches_oracle(dtype):
     torch, dfl = _gpu()
     U, fld = field()
     prop = random_prop(DIMS, 5001, dtype)
-    for t0 in (0, 5):
+    for t0 in (0, 5, DIMS[0] - 1):
         got = dfl.nucleon_2pt(fld, torch.from_numpy(prop).cuda(), t0).cpu().numpy()
         ref = nuc.nucleon_2pt(prop.astype(np.complex128), DIMS, t0)
         err = relmax(got, ref)
@@ -64,13 +64,14 @@ def test_two_point_contraction_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("flavour", ["u", "d"])
-@pytest.mark.parametrize("direction", ["forward", "backward"])
-def test_sequential_sources_match_oracle(flavour, direction):
+@pytest.mark.parametrize("direction,t_s", [("forward", 6), ("backward", 2), ("forward", DIMS[0] - 1),
+                                           ("backward", 0)])
+def test_sequential_sources_match_oracle(flavour, direction, t_s):
     torch, dfl = _gpu()
     U, fld = field()
     prop = random_prop(DIMS, 5002)
     Pp, Pm = nuc.parity_projectors()
-    t_s, P = (6, Pp) if direction == "forward" else (2, Pm)
+    P = Pp if direction == "forward" else Pm
     got = dfl.nucleon_seq_sources(fld, torch.from_numpy(prop).cuda(), t_s, P, flavour).cpu().numpy()
     ref = nuc.nucleon_seq_sources(prop, DIMS, t_s, P, flavour)
     spatial = synth.volume(DIMS) // DIMS[0]

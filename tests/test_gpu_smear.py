@@ -68,3 +68,22 @@ def test_gauss_smearing_matches_oracle(dtype):
     # the smeared point source stays on its timeslice
     t = np.arange(V) // (V // DIMS[0])
     assert np.abs(got[0][t != 3]).max() == 0
+
+
+def test_smearing_degenerate_parameters():
+    """Zero iterations and zero strength are the identity: APE with n = 0 or
+    alpha = 0 returns the original spatial links (SU(3) links are their own
+    polar factor, to rounding), Gaussian smearing with n = 0 or kappa_G = 0
+    returns its input exactly."""
+    torch, dfl = _gpu()
+    s = state()
+    U = s["U"]
+    for alpha, n in ((0.5, 0), (0.0, 3)):
+        s["fld"].ape_smear(alpha, n)
+        got = s["fld"].ape_links().cpu().numpy()
+        assert np.abs(got - U[:, 1:]).max() <= 1e-13, (alpha, n)
+    x = torch.from_numpy(synth.gaussian_spinor(DIMS, 2, 6002)).cuda()
+    for kappa, n in ((0.4, 0), (0.0, 5)):
+        assert torch.equal(dfl.gauss_smear(s["fld"], x, kappa, n), x), (kappa, n)
+    # back to the parameters the other tests use
+    s["fld"].ape_smear(ALPHA, NAPE)
