@@ -58,13 +58,14 @@ typedef enum { QCD_F64 = 0, QCD_F32 = 1, QCD_F16 = 2, QCD_BF16 = 3 } qcd_prec;
 
 /* Lattice, operator parameters and the Schwarz block grid.  The block grid
  * fixes the library's internal site order (block-major, parity split), so a
- * field handle serves one block size; SAP and deflation use it.  Each block
+ * field handle serves one Schwarz block size; deflation uses it too unless
+ * deflation_setup is given a larger multiple of it.  Each block
  * extent must be even and divide the lattice extent, and the number of
  * blocks in every direction must be even so that the two-colour checkerboard
  * of blocks (Omega, Omega*, section 2.2) closes periodically. */
 typedef struct {
     int dims[4];     /* T, X, Y, Z */
-    int block[4];    /* Schwarz / deflation block extents */
+    int block[4];    /* Schwarz block extents (and the default deflation block) */
     double kappa;
     double csw;
     int bc_t;        /* -1: antiperiodic in time (fermions), +1: periodic */
@@ -289,8 +290,8 @@ int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const 
  * field beforehand).  All sets are validated before the first launch; the
  * fields are then solved in order on `stream`, each field's solver work
  * buffers (and captured graphs) released to the library's cache once its
- * set is done, so the peak memory is that of the largest field.  All handles must live on
- * the current device. */
+ * set is done, so that the work buffers peak at what the largest field
+ * needs.  All handles must live on the current device. */
 int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, void *const *const *x_sloppy,
                     void *const *const *x_exact, qcd_prec io, qcd_info *const *info_sloppy,
                     qcd_info *const *info_exact, hipStream_t stream);
@@ -304,9 +305,9 @@ int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, vo
  * into a HIP graph (on a stream the handle owns) and replayed for every
  * later batch of that size, on `stream`.  Little solves inside then run
  * a fixed budget: p->little_maxit iterations in P_R, and one cycle of
- * max(24, p->little_maxit) iterations in the low-mode correction.  info[r].rel_res is the FP64
- * relative residual after the fixed iterations; status QCD_NOCONV if it is
- * above p->res.  Graphs are kept in the handle until a workspace buffer
+ * max(24, p->little_maxit) iterations in the low-mode correction.
+ * info[r].rel_res is the FP64 relative residual after the fixed
+ * iterations; status QCD_NOCONV if it is above p->res.  Graphs are kept in the handle until a workspace buffer
  * grows or the handle is destroyed.  Calls must not overlap in time with
  * other calls on the same handle. */
 int gcr_solve_batched(qcd_field f, const qcd_gcr *p, const void *const *b, void *const *x, int nrhs, qcd_prec io,
