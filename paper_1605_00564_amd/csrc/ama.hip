@@ -30,16 +30,17 @@ __global__ void k_point_sources(double2 *__restrict__ b, const int *__restrict__
 // the available memory cannot hold it, and then to an even count (the
 // Schwarz and stencil kernels take right-hand sides in pairs).  Available:
 // free device memory, the library's cached workspace and the handle's own
-// buffers.  Memory only: per right-hand side the results do not depend on
-// the batch.
-int pick_batch(qcd_field f, const qcd_gcr &p, int want) {
+// buffers except slot `busy` (one the caller keeps using).  Memory only: per
+// right-hand side the results do not depend on the batch.
+int pick_batch(qcd_field f, const qcd_gcr &p, int want, int busy) {
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) {
         (void)hipGetLastError();
         return want > 0 ? want : 12;
     }
     freeb += ws_cached_bytes(f->device);
-    for (size_t k = 0; k < sizeof(f->buf_bytes) / sizeof(f->buf_bytes[0]); ++k) freeb += f->buf_bytes[k];
+    for (int k = 0; k < (int)(sizeof(f->buf_bytes) / sizeof(f->buf_bytes[0])); ++k)
+        if (k != busy) freeb += f->buf_bytes[k];
     const size_t V = f->g.V;
     const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
     const size_t per = std::max<size_t>(V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5), 1);

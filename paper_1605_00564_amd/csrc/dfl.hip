@@ -890,7 +890,8 @@ int inverse_iteration(qcd_dfl d, float4 *v, hipStream_t s) {
     q.dfl = d;
     q.little_tol = 1e-8;
     q.little_maxit = 16;
-    const int nb = std::max(1, std::min(Ns, pick_batch(f, q, 0)));
+    // the global fields stay in the handle's source buffer during the solves
+    const int nb = std::max(1, std::min(Ns, pick_batch(f, q, 0, BUF_AMA)));
     void *p;
     DFL_TRY(field_buffer(f, BUF_APPLY, 2 * spinor_bytes(QCD_F64, V) * nb, &p));
     double2 *b64 = static_cast<double2 *>(p), *x64 = b64 + (size_t)12 * V * nb;

@@ -698,8 +698,10 @@ int gcr_internal(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, in
 // solution misses p.res
 // right-hand sides per solver launch for parameters p: want (> 0), lowered
 // to an even count only if 90% of the available memory cannot hold it, or
-// (want = 0) what 60% of it holds, at most 48 and a multiple of 12 when possible
-int pick_batch(qcd_field f, const qcd_gcr &p, int want);
+// (want = 0) what 60% of it holds, at most 48 and a multiple of 12 when
+// possible; available: free memory, the workspace cache and the handle's
+// buffers other than slot `busy`
+int pick_batch(qcd_field f, const qcd_gcr &p, int want, int busy = -1);
 int solve_batch(qcd_field f, const qcd_gcr &p, const double2 *b64, double2 *x64, int n, bool graph, qcd_info *info,
                 hipStream_t s, int &status);
 // canonical <-> internal conversion; canon is complex128 (F64) or complex64 (F32)
