@@ -341,17 +341,26 @@ def post_solve(fld, prop, t0, log, ape=(0.5, 20), gauss=(3.0, 30)):
     launch: APE step 6 x 144 B per site (3 spatial FP64 links read and
     written); Gauss step 12 x 2 x 192 B + 3 x 144 B per site; two-point 2304
     B per site; sequential sources 2304 B per sink-timeslice site read and
-    2304 B per site written; three-point 2 x 2304 B per site."""
+    2304 B per site written; three-point 2 x 2304 B per site.  Each entry
+    carries a roofline: HBM for the streaming kernels, FP64 ALU for the
+    two-point contraction (28 800 flop per site)."""
     import torch
     import paper_1605_00564_amd as dfl
     V, T = fld.V, fld.dims[0]
     L3 = V // T
     out = {}
 
-    def rec(name, ms, nbytes, **extra):
-        out[name] = {"ms": ms, "GB/s": nbytes / (ms * 1e-3) / 1e9, "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                     "bytes": nbytes, **extra}
-        log(f"[post] {name}: {ms:.3f} ms, {out[name]['GB/s']:.0f} GB/s algorithmic")
+    def rec(name, ms, nbytes, flops=None, **extra):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "GB/s": gbs, "frac_hbm": gbs / PEAK_HBM_GBS, "bytes": nbytes, **extra}
+        if flops is None:
+            out[name]["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                     "frac": gbs / PEAK_HBM_GBS}
+        else:
+            tf = flops / (ms * 1e-3) / 1e12
+            out[name]["roofline"] = {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                     "frac": tf / PEAK_FP64_TFLOPS, "flops": flops}
+        log(f"[post] {name}: {ms:.3f} ms, {gbs:.0f} GB/s algorithmic")
 
     alpha, n_ape = ape
     ms = _event_ms(lambda: fld.ape_smear(alpha, n_ape), 2)
@@ -361,7 +370,8 @@ def post_solve(fld, prop, t0, log, ape=(0.5, 20), gauss=(3.0, 30)):
     ms = _event_ms(lambda: dfl.gauss_smear(fld, prop, kg, n_g, out=sm), 2)
     rec("gauss_smear", ms / n_g, (12 * 2 * 192 + 3 * 144) * V, kappa=kg, iterations=n_g, per="iteration, 12 vectors")
     ms = _event_ms(lambda: dfl.nucleon_2pt(fld, sm, t0), 5)
-    rec("nucleon_2pt", ms, 2304 * V)
+    # FP64 arithmetic, 3600 complex multiply-adds per site (the colour sums factored)
+    rec("nucleon_2pt", ms, 2304 * V, flops=28800.0 * V)
     for flav in ("u", "d"):
         for tag, ts, P in (("forward", (t0 + T // 4) % T, P_PLUS), ("backward", (t0 - T // 4) % T, P_MINUS)):
             ms = _event_ms(lambda: dfl.nucleon_seq_sources(fld, sm, ts, P, flav), 5)
@@ -375,6 +385,46 @@ def post_solve(fld, prop, t0, log, ape=(0.5, 20), gauss=(3.0, 30)):
     rec("ama_combine", ms, (32 + 2) * T * 16 * 16)
     del seq, sm, g, e
     return out
+
+
+def post_solve_oracle(work, log, ape=(0.5, 20), gauss=(3.0, 30)):
+    """The oracle's versions of the steps after the solve (FP64 numpy) timed
+    on the host on a bounded sample, an 8^4 lattice with the workload's
+    field recipe, and scaled per site to the workload's lattice: two-point
+    and three-point contractions and the APE and Gauss steps per site, the
+    sequential sources per sink-timeslice site."""
+    import oracle
+    from oracle import nucleon as nuc, smear
+    dims = (8, 8, 8, 8)
+    Vs = synth.volume(dims)
+    V = synth.volume(work["dims"])
+    L3 = V // work["dims"][0]
+    prop = synth.gaussian_spinor(dims, 12, 5)
+    U = synth.gauge_field(dims, work["eps"], work["seed"])
+    g, _ = oracle.gamma_matrices()
+    Pp, _ = nuc.parity_projectors()
+    out = {}
+
+    def timed(fn):
+        t = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t, r
+
+    t, Us = timed(lambda: smear.ape_smear(dims, U, ape[0], 2))
+    out["ape_smear"] = 1e3 * t / 2 / Vs * V
+    t, _ = timed(lambda: smear.gauss_smear(dims, Us, prop, gauss[0], 2))
+    out["gauss_smear"] = 1e3 * t / 2 / Vs * V
+    t, _ = timed(lambda: nuc.nucleon_2pt(prop, dims, 0))
+    out["nucleon_2pt"] = 1e3 * t / Vs * V
+    t, seq = timed(lambda: nuc.nucleon_seq_sources(prop, dims, 2, Pp, "u"))
+    out["nucleon_seq_u_forward"] = 1e3 * t / (Vs // dims[0]) * L3
+    t, _ = timed(lambda: nuc.nucleon_3pt(seq, prop, dims, 0, g[3] @ g[4]))
+    out["nucleon_3pt"] = 1e3 * t / Vs * V
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log("[post] oracle, scaled to the workload: " + ", ".join(f"{k} {v:.0f} ms" for k, v in out.items()))
+    return {"ms_scaled": out, "kind": "oracle", "cores": threads,
+            "sample": "8^4 lattice (same field recipe), one call each (APE and Gauss: 2 steps), scaled per site "
+                      "(sequential sources per sink-timeslice site) to the workload; per APE / Gauss step"}
 
 
 def run_config3(args, log):
@@ -835,6 +885,8 @@ def main():
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         result["cpu_baseline"] = cpu_baseline(work, block, {c: prof[c] for c in prof}, npos * args.steps, 5, 4,
                                               threads)
+        if "post_solve" in result:
+            result["post_solve"]["oracle_cpu"] = post_solve_oracle(work, log)
     print(json.dumps(result), flush=True)
 
 

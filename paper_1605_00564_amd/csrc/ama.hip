@@ -114,7 +114,7 @@ int check_set(const Geom &g, const qcd_ama *a) {
     return 0;
 }
 
-// default right-hand sides per batch: as many as fit a modest share of HBM
+// bytes of one canonical vector at precision p
 size_t canon_bytes(qcd_prec p, long V) { return (p == QCD_F64 ? 16 : 8) * (size_t)12 * V; }
 
 // b64[0..n) = sources of list[r0 .. r0+n)
