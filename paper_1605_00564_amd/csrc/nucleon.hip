@@ -18,6 +18,7 @@
 // timeslice), so results do not depend on the launch order.
 #include <complex>
 
+#include "blas.h"
 #include "internal.h"
 
 namespace dfl {
@@ -213,14 +214,16 @@ __device__ inline double eps3(int i, int j, int k) {
 // zero elsewhere, with K = d tr(P C(x)) / d S_f(x) (flavour d: one line; u:
 // the two lines, four occurrences).  i = (spin g, colour e) at the sink,
 // j = 3 h + e' at the source.  The 3 x 3 colour blocks K^{ee'} are computed
-// one at a time, each from the Wick terms in which the differentiated line
-// carries the colours (e, e').
+// each by its own thread, from the Wick terms in which the differentiated
+// line carries the colours (e, e').  Threads cover the sink timeslice only,
+// nine per site (the other timeslices are zeroed by a fill beforehand).
 template <class CT>
 __global__ void __launch_bounds__(128) k_nucleon_seq(const CT *__restrict__ prop, CT *__restrict__ eta, long V,
                                                      long spatial, int t_sink, Mono4 G, Mat4 P, int flavour) {
-    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= V) return;
-    const bool on = x / spatial == t_sink;
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= 9 * spatial) return;
+    const long x = (long)t_sink * spatial + tid / 9;
+    const int e = (int)(tid % 9) / 3, ep = (int)(tid % 3);
     const Prop<CT> S{prop, V, (unsigned long long)x};
     auto pm = [&](int i, int j) { return cd{P.re[4 * i + j], P.im[4 * i + j]}; };
     // tr(P S^{aa'}) = sum_{ij} P_{ji} S^{aa'}_{ij}
@@ -242,14 +245,13 @@ __global__ void __launch_bounds__(128) k_nucleon_seq(const CT *__restrict__ prop
                 Q[s][sp] = (mono_g(G, s) * mono_g(G, q)) * S(G.pi[s], b, q, bp);
             }
     };
-    for (int e = 0; e < 3; ++e)
-        for (int ep = 0; ep < 3; ++ep) {
+    {
             cd K[4][4];
 #pragma unroll
             for (int g = 0; g < 4; ++g)
 #pragma unroll
                 for (int h = 0; h < 4; ++h) K[g][h] = {0.0, 0.0};
-            if (on && flavour == 1) {
+            if (flavour == 1) {
                 // d line with colours (b, b') = (e, e'):
                 //   eps eps [ tr(P U^{cc'}) (G^T U^{aa'} G^T) - G^T U^{ac'} P U^{ca'} G^T ]
                 for (int a = 0; a < 3; ++a)
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(128) k_nucleon_seq(const CT *__restrict__ prop
                             }
                         }
                     }
-            } else if (on) {
+            } else {
                 // u line with colours (e, e'), in each of its four places
                 for (int b = 0; b < 3; ++b)
                     for (int bp = 0; bp < 3; ++bp) {
@@ -537,14 +539,18 @@ extern "C" int nucleon_seq_sources(qcd_field f, const void *prop, qcd_prec io, i
     const Mono4 G = cg5_mono();
     const Mat4 P = mat4(proj);
     ProfScope ps(PROF_OTHER, s);
+    // zero everywhere (a coalesced fill: 12 vectors x V sites x 12 complex),
+    // then the sink timeslice
+    const size_t bytes = (size_t)12 * V * 12 * (io == QCD_F64 ? 16 : 8);
+    DFL_TRY(blas_zero<double2>(static_cast<double2 *>(eta), (long)(bytes / 16), 1, s));
     if (io == QCD_F64)
-        k_nucleon_seq<double2><<<nblocks(V, 128), 128, 0, s>>>(static_cast<const double2 *>(prop),
-                                                               static_cast<double2 *>(eta), V, spatial, t_sink, G, P,
-                                                               flavour);
+        k_nucleon_seq<double2><<<nblocks(9 * spatial, 128), 128, 0, s>>>(static_cast<const double2 *>(prop),
+                                                                         static_cast<double2 *>(eta), V, spatial,
+                                                                         t_sink, G, P, flavour);
     else
-        k_nucleon_seq<float2><<<nblocks(V, 128), 128, 0, s>>>(static_cast<const float2 *>(prop),
-                                                              static_cast<float2 *>(eta), V, spatial, t_sink, G, P,
-                                                              flavour);
+        k_nucleon_seq<float2><<<nblocks(9 * spatial, 128), 128, 0, s>>>(static_cast<const float2 *>(prop),
+                                                                        static_cast<float2 *>(eta), V, spatial,
+                                                                        t_sink, G, P, flavour);
     DFL_HIP(hipGetLastError());
     return 0;
 }
