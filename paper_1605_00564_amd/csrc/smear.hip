@@ -91,10 +91,14 @@ __device__ inline void project_su3(cd w[9]) {
     for (int k = 0; k < 9; ++k) w[k] = w[k] * ph;
 }
 
-// one APE step on the spatial links Uin [3][9][V] -> Uout (internal order)
+// one APE step on the spatial links Uin [3][9][V] -> Uout (internal order);
+// each XCD takes a contiguous range of site tiles, so that the staples'
+// neighbour links come through its L2
 __global__ void __launch_bounds__(128) k_ape_step(const double2 *__restrict__ Uin, double2 *__restrict__ Uout,
                                                   const int *__restrict__ nbr, long V, double alpha) {
-    const long xl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned bx, by;
+    xcd_order(bx, by);
+    const long xl = (long)bx * blockDim.x + threadIdx.x;
     if (xl >= V) return;
     const unsigned x = (unsigned)xl;
     for (int i = 0; i < 3; ++i) {
@@ -133,14 +137,19 @@ __global__ void __launch_bounds__(128) k_ape_step(const double2 *__restrict__ Ui
     }
 }
 
-// one Gaussian step on n internal FP64 vectors ([n][12][V])
+// one Gaussian step on n internal FP64 vectors ([n][12][V]): one thread per
+// site and vector; the workgroups of one site tile (all vectors) run back to
+// back on one XCD, so that they share the tile's links through its L2
+// (threads that take two vectors to load the links once need 256 registers)
 __global__ void __launch_bounds__(128) k_gauss_step(const double2 *__restrict__ in, double2 *__restrict__ out,
                                                     const double2 *__restrict__ U, const int *__restrict__ nbr, long V,
                                                     double kappa, double norm) {
-    const long xl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned bx, by;
+    xcd_order(bx, by);
+    const long xl = (long)bx * blockDim.x + threadIdx.x;
     if (xl >= V) return;
     const unsigned x = (unsigned)xl;
-    const double2 *src = in + (size_t)blockIdx.y * 12 * V;
+    const double2 *src = in + (size_t)by * 12 * V;
     cd acc[12], p[12], w[9];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -178,7 +187,7 @@ __global__ void __launch_bounds__(128) k_gauss_step(const double2 *__restrict__ 
                 acc[3 * s + a] = rmac(acc[3 * s + a], kappa, v);
             }
     }
-    double2 *dst = out + (size_t)blockIdx.y * 12 * V;
+    double2 *dst = out + (size_t)by * 12 * V;
 #pragma unroll
     for (int k = 0; k < 12; ++k) dst[(size_t)k * V + x] = make_double2(norm * acc[k].re, norm * acc[k].im);
 }
