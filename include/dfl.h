@@ -186,9 +186,12 @@ int deflation_dims(qcd_dfl d, int *Nb, int *Ns);
 /* w = A v for nrhs little vectors, complex128 DEVICE [nrhs][Nb][Ns] with the
  * block order of deflation_get_phi. */
 int little_dirac_apply(qcd_dfl d, const void *v, void *w, int nrhs, hipStream_t stream);
-/* w = A^{-1} v by FP64 GCR on A with block-Jacobi preconditioning, to
- * relative residual tol (or maxit iterations); iters (host, may be NULL)
- * receives the iteration count. */
+/* w = A^{-1} v in FP64 by the block even-odd Schur complement (blocks
+ * coloured by the parity of their coordinates on the deflation-block grid):
+ * GCR on S = A_EE - A_EO A_OO^{-1} A_OE preconditioned with the inverse
+ * diagonal blocks A_EE^{-1}, then x_O = A_OO^{-1} (v_O - A_OE x_E); to
+ * relative residual ||v - A w|| / ||v|| <= tol (or maxit iterations); iters
+ * (host, may be NULL) receives the iteration count. */
 int little_dirac_solve(qcd_dfl d, const void *v, void *w, int nrhs, double tol, int maxit, int *iters,
                        hipStream_t stream);
 /* Phi^+ v (restriction, complex128 [nrhs][Nb][Ns]) and Phi c

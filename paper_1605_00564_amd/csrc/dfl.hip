@@ -1,7 +1,8 @@
 // Block-local deflation (section 2.2): subspace from Ns global fields
 // restricted to the Schwarz blocks and orthonormalised per block, the little
 // Dirac operator A_kl = (phi_k, M phi_l) (eq. little), restriction Phi^+ v,
-// prolongation Phi c, and the little solve A^{-1} by block-Jacobi GCR.
+// prolongation Phi c, and the little solve A^{-1} by GCR on the block
+// even-odd Schur complement.
 #include <cmath>
 
 #include "blas.h"
@@ -428,36 +429,43 @@ __global__ void __launch_bounds__(256) k_prolong(E *__restrict__ v, const float4
     }
 }
 
-// w[r][B] = sum_{d < ND} M[B][d] v[r][nb(B, d)] with Ns x Ns complex blocks
-// M[B][d] (ND = 9: the little operator, neighbour d of block B from the
-// table; ND = 1: the block-Jacobi inverse acting on block B itself).  Per
-// block this is a complex GEMM (Ns x ND Ns) (ND Ns x n) on the FP64 matrix
-// cores: a wave owns one block, 16 rows and 16 right-hand sides, and with
-// M = a + ib, v = c + id accumulates Re w = a c - b d and Im w = a d + b c
-// as real 16x16x4 products over four complex elements of K at a time.  Lane
-// L supplies M[row L % 16][k L / 16] and v[k L / 16][rhs L % 16] and
-// receives w[row L / 16 + 4 i][rhs L % 16], i = 0..3 (the FP64 product's
-// result layout; the FP32 16x16x4 product returns row 4 (L / 16) + i).
+// w[r][B] = sgn sum_{d0 <= d < ND} M[B][d] v_d[r][nb(B, d)] with Ns x Ns
+// complex blocks M[B][d] (ND = 9: the little operator, neighbour d of block B
+// from the table; ND = 1: the block-Jacobi inverse acting on block B
+// itself).  The self block (d = 0) reads vs, the neighbours vn (the same
+// array for a plain product); d0 = 1 leaves the self block out.  Rows: the
+// blocks listed in rows[0..nrows) (all Nb blocks when rows is null); other
+// blocks of w are not written.  Per block this is a complex GEMM
+// (Ns x ND Ns) (ND Ns x n) on the FP64 matrix cores: a wave owns one block,
+// 16 rows and 16 right-hand sides, and with M = a + ib, v = c + id
+// accumulates Re w = a c - b d and Im w = a d + b c as real 16x16x4 products
+// over four complex elements of K at a time.  Lane L supplies
+// M[row L % 16][k L / 16] and v[k L / 16][rhs L % 16] and receives
+// w[row L / 16 + 4 i][rhs L % 16], i = 0..3 (the FP64 product's result
+// layout; the FP32 16x16x4 product returns row 4 (L / 16) + i).
 template <int ND>
 __global__ void __launch_bounds__(256) k_little_mfma(const double2 *__restrict__ M, const int *__restrict__ bnbr,
-                                                     const double2 *__restrict__ v, double2 *__restrict__ w,
-                                                     int Nb, int Ns, int n, int nmt, int nrt) {
+                                                     const double2 *__restrict__ vs, const double2 *__restrict__ vn,
+                                                     double2 *__restrict__ w, const int *__restrict__ rows,
+                                                     int nrows, int d0, double sgn, int Nb, int Ns, int n, int nmt,
+                                                     int nrt) {
     const int lane = threadIdx.x & 63;
     const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const long per_block = (long)nmt * nrt;
-    if (wid >= (long)Nb * per_block) return;
-    const int B = (int)(wid / per_block);
-    const int rem = (int)(wid - (long)B * per_block);
+    if (wid >= (long)nrows * per_block) return;
+    const int ri = (int)(wid / per_block);
+    const int B = rows ? rows[ri] : ri;
+    const int rem = (int)(wid - (long)ri * per_block);
     const int m0 = (rem / nrt) * 16, r0 = (rem % nrt) * 16;
     const int row = lane & 15, kk = lane >> 4;
     const int m = m0 + row, r = r0 + row;
     const bool mv = m < Ns, rv = r < n;
     const size_t N = (size_t)Nb * Ns;
     d4v ac = {0, 0, 0, 0}, bd = {0, 0, 0, 0}, ad = {0, 0, 0, 0}, bc = {0, 0, 0, 0};
-    for (int d = 0; d < ND; ++d) {
+    for (int d = d0; d < ND; ++d) {
         const double2 *Md = M + ((size_t)B * ND + d) * Ns * Ns + (size_t)(mv ? m : 0) * Ns;
-        const int nb = ND == 1 ? B : bnbr[B * 9 + d];
-        const double2 *vd = v + (size_t)(rv ? r : 0) * N + (size_t)nb * Ns;
+        const int nb = (ND == 1 || d == 0) ? B : bnbr[B * 9 + d];
+        const double2 *vd = (d == 0 ? vs : vn) + (size_t)(rv ? r : 0) * N + (size_t)nb * Ns;
         for (int l0 = 0; l0 < Ns; l0 += 4) {
             const int l = l0 + kk;
             double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
@@ -475,8 +483,19 @@ __global__ void __launch_bounds__(256) k_little_mfma(const double2 *__restrict__
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int mo = m0 + kk + 4 * i;
-        if (mo < Ns) w[(size_t)r * N + (size_t)B * Ns + mo] = make_double2(ac[i] - bd[i], ad[i] + bc[i]);
+        if (mo < Ns)
+            w[(size_t)r * N + (size_t)B * Ns + mo] = make_double2(sgn * (ac[i] - bd[i]), sgn * (ad[i] + bc[i]));
     }
+}
+
+// v[r][B] = 0 for the blocks B listed in rows[0..nrows)
+__global__ void k_zero_rows(double2 *__restrict__ v, const int *__restrict__ rows, int nrows, int Nb, int Ns, int n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)n * nrows * Ns) return;
+    const int k = (int)(i % Ns);
+    const long rb = i / Ns;
+    const int ri = (int)(rb % nrows), r = (int)(rb / nrows);
+    v[((size_t)r * Nb + rows[ri]) * Ns + k] = make_double2(0.0, 0.0);
 }
 
 // Dinv[B] = A[B][0]^{-1}: Gauss-Jordan with partial pivoting, one thread per
@@ -673,10 +692,13 @@ int prolong_v(qcd_dfl d, E *v, const double2 *c, int n, hipStream_t s) {
 }
 
 template <int ND>
-static int launch_little(qcd_dfl d, const double2 *M, const double2 *v, double2 *w, int n, hipStream_t s) {
+static int launch_little(qcd_dfl d, const double2 *M, const double2 *vs, const double2 *vn, double2 *w, int n,
+                         hipStream_t s, const int *rows = nullptr, int nrows = -1, int d0 = 0, double sgn = 1.0) {
+    if (nrows < 0) nrows = d->Nb;
     const int nmt = (d->Ns + 15) / 16, nrt = (n + 15) / 16;
-    const long waves = (long)d->Nb * nmt * nrt;
-    k_little_mfma<ND><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(M, d->bnbr, v, w, d->Nb, d->Ns, n, nmt, nrt);
+    const long waves = (long)nrows * nmt * nrt;
+    k_little_mfma<ND><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(M, d->bnbr, vs, vn, w, rows, nrows, d0, sgn, d->Nb,
+                                                                  d->Ns, n, nmt, nrt);
     DFL_HIP(hipGetLastError());
     return 0;
 }
@@ -687,18 +709,54 @@ int little_apply_dev(qcd_dfl d, const double2 *v, double2 *w, int n, hipStream_t
     // right-hand sides, v and w once per rhs
     ProfScope ps(PROF_LITTLE, s, 8.0 * 9 * d->Ns * N * n,
                  16.0 * (9.0 * d->Ns * N * ((n + 15) / 16) + 2.0 * N * n), (double)N * n);
-    return launch_little<9>(d, d->A, v, w, n, s);
+    return launch_little<9>(d, d->A, v, v, w, n, s);
 }
 
-int little_jacobi_dev(qcd_dfl d, const double2 *v, double2 *z, int n, hipStream_t s) {
+// one colour's block rows of A (d0 = 1: without the self block) or of the
+// block-Jacobi inverse, times sgn; the work accounting per row as for the
+// full product
+static int little_rows(qcd_dfl d, bool inverse, const double2 *vs, const double2 *vn, double2 *w, int n, int colour,
+                       int d0, double sgn, hipStream_t s) {
+    const int nh = d->Nb / 2;
+    const double rows = (double)nh * d->Ns;
+    const double nd = inverse ? 1.0 : 9.0 - d0;
+    ProfScope ps(PROF_LITTLE, s, 8.0 * nd * d->Ns * rows * n,
+                 16.0 * (nd * d->Ns * rows * ((n + 15) / 16) + 2.0 * rows * n), rows * n);
+    const int *rl = d->brow + (size_t)colour * nh;
+    if (inverse) return launch_little<1>(d, d->Dinv, vs, vn, w, n, s, rl, nh, 0, sgn);
+    return launch_little<9>(d, d->A, vs, vn, w, n, s, rl, nh, d0, sgn);
+}
+
+static int zero_rows(qcd_dfl d, double2 *v, int n, int colour, hipStream_t s) {
+    const int nh = d->Nb / 2;
+    k_zero_rows<<<nblocks((long)n * nh * d->Ns, 256), 256, 0, s>>>(v, d->brow + (size_t)colour * nh, nh, d->Nb,
+                                                                   d->Ns, n);
+    DFL_HIP(hipGetLastError());
+    return 0;
+}
+
+// w = S v_E on the even blocks, S = A_EE - A_EO A_OO^{-1} A_OE (only v's
+// even blocks are read; w's odd blocks are zero); t, q: work vectors
+static int schur_apply(qcd_dfl d, const double2 *v, double2 *w, double2 *t, double2 *q, int n, hipStream_t s) {
     const long N = (long)d->Nb * d->Ns;
-    ProfScope ps(PROF_LITTLE, s, 8.0 * d->Ns * N * n, 16.0 * ((double)d->Ns * N * ((n + 15) / 16) + 2.0 * N * n),
-                 (double)N * n);
-    return launch_little<1>(d, d->Dinv, v, z, n, s);
+    DFL_TRY(little_rows(d, false, v, v, t, n, 1, 1, 1.0, s));      // t_O = A_OE v_E
+    DFL_TRY(little_rows(d, true, t, t, q, n, 1, 0, -1.0, s));      // q_O = -A_OO^{-1} t_O
+    DFL_TRY(blas_zero<double2>(w, N, n, s));
+    return little_rows(d, false, v, q, w, n, 0, 0, 1.0, s);        // w_E = A_EE v_E + A_EO q_O
 }
 
-// x = A^{-1} u by block-Jacobi preconditioned GCR (FP64).  poll: check the
-// residual on the host after every iteration and stop at tol; otherwise run
+// x = A^{-1} u (FP64) by the block even-odd Schur complement.  Blocks are
+// coloured by the parity of their coordinates on the deflation-block grid
+// (an even number of blocks along every axis), so every coupling of A joins
+// blocks of opposite colour and A_EE, A_OO are block diagonal:
+//   u'_E = u_E - A_EO A_OO^{-1} u_O,
+//   S x_E = u'_E, S = A_EE - A_EO A_OO^{-1} A_OE, by GCR preconditioned
+//   with A_EE^{-1} (the block-Jacobi factors of the even blocks),
+//   x_O = A_OO^{-1} (u_O - A_OE x_E).
+// Vectors are full length [n][Nb][Ns]; the Krylov space lives on the even
+// blocks.  The residual of the full system equals that of the Schur system
+// (x_O is exact given x_E), and it is reported relative to ||u||.  poll:
+// check it on the host after every iteration and stop at tol; otherwise run
 // one cycle of min(maxit, nkv) iterations without host synchronisation.
 int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int maxit, bool poll, int *iters_out,
                  double *relres_out, hipStream_t s) {
@@ -707,15 +765,17 @@ int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int
     const long N = (long)d->Nb * d->Ns;
     const int nkv = std::max(1, std::min(maxit, 24));
     const size_t vb = sizeof(double2) * N * n;
-    const size_t need = vb * (2 * (size_t)nkv + 2) + scalar_bytes(n);
+    const size_t need = vb * (2 * (size_t)nkv + 4) + scalar_bytes(n);
     void *p;
     DFL_TRY(dfl_work(d, need, &p));
     double2 *Z = static_cast<double2 *>(p);
     double2 *W = Z + (size_t)nkv * n * N;
     double2 *r = W + (size_t)nkv * n * N;
     double2 *t = r + (size_t)n * N;
+    double2 *q = t + (size_t)n * N;
+    double2 *us = q + (size_t)n * N;      // the Schur right-hand side u'
     Scal sc;
-    DFL_TRY(scalar_buffers_at(t + (size_t)n * N, n, sc));
+    DFL_TRY(scalar_buffers_at(us + (size_t)n * N, n, sc));
     std::vector<double> bn(n, 0.0), h(n);
     auto fetch = [&](const double *dev) -> int {
         DFL_HIP(hipMemcpyAsync(d->hp, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -728,8 +788,14 @@ int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int
         DFL_TRY(fetch(sc.red));
         for (int i = 0; i < n; ++i) bn[i] = std::sqrt(h[i]);
     }
+    // u'_E = u_E - A_EO A_OO^{-1} u_O (odd blocks zero); r = u', x = 0
+    DFL_TRY(little_rows(d, true, u, u, q, n, 1, 0, 1.0, s));       // q_O = A_OO^{-1} u_O
+    DFL_TRY(blas_zero<double2>(t, N, n, s));
+    DFL_TRY(little_rows(d, false, q, q, t, n, 0, 1, 1.0, s));      // t_E = A_EO q_O
+    DFL_TRY(blas_resid(u, t, us, N, n, sc.part, sc.red, s));       // us = u - t
+    DFL_TRY(zero_rows(d, us, n, 1, s));
+    DFL_HIP(hipMemcpyAsync(r, us, vb, hipMemcpyDeviceToDevice, s));
     DFL_TRY(blas_zero<double2>(x, N, n, s));
-    DFL_HIP(hipMemcpyAsync(r, u, vb, hipMemcpyDeviceToDevice, s));
     int iters = 0;
     double worst = 0;
     bool done = false;
@@ -737,8 +803,9 @@ int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int
         int k = 0;
         while (k < nkv && iters < maxit) {
             double2 *zk = Z + (size_t)k * n * N, *wk = W + (size_t)k * n * N;
-            DFL_TRY(little_jacobi_dev(d, r, zk, n, s));
-            DFL_TRY(little_apply_dev(d, zk, wk, n, s));
+            // z = A_EE^{-1} r on the even blocks (the odd blocks of z are never read)
+            DFL_TRY(little_rows(d, true, r, r, zk, n, 0, 0, 1.0, s));
+            DFL_TRY(schur_apply(d, zk, wk, t, q, n, s));
             int bstride = 2;
             if (k > 0) bstride = blas_multidot<double2>(W, N, n, k, sc.part, sc.red2, s);
             if (bstride < 0) return bstride;
@@ -765,11 +832,15 @@ int little_solve(qcd_dfl d, const double2 *u, double2 *x, int n, double tol, int
         DFL_TRY(gcr_trisolve(sc.R, sc.cvec, n, k, sc.alpha, s));
         DFL_TRY(blas_accum_d(x, Z, N, n, k, sc.alpha, 2 * NKV_MAX, s));
         if (!poll) break;
-        if (!done && iters < maxit) {  // restart from the true residual
-            DFL_TRY(little_apply_dev(d, x, t, n, s));
-            DFL_TRY(blas_resid(u, t, r, N, n, sc.part, sc.red, s));
+        if (!done && iters < maxit) {  // restart from the true Schur residual
+            DFL_TRY(schur_apply(d, x, t, q, W, n, s));   // the Krylov vectors are free at a restart
+            DFL_TRY(blas_resid(us, t, r, N, n, sc.part, sc.red, s));
         }
     }
+    // x_O = A_OO^{-1} (u_O - A_OE x_E)
+    DFL_TRY(little_rows(d, false, x, x, t, n, 1, 1, 1.0, s));      // t_O = A_OE x_E
+    DFL_TRY(blas_resid(u, t, q, N, n, sc.part, sc.red, s));        // q = u - t (odd blocks used)
+    DFL_TRY(little_rows(d, true, q, q, x, n, 1, 0, 1.0, s));       // x_O = A_OO^{-1} q_O
     if (iters_out) *iters_out = iters;
     if (relres_out) *relres_out = worst;
     return (poll && !done) ? QCD_NOCONV : 0;
@@ -830,6 +901,7 @@ void dfl_free(qcd_dfl d) {
     (void)hipFree(d->A);
     (void)hipFree(d->Dinv);
     (void)hipFree(d->bnbr);
+    (void)hipFree(d->brow);
     (void)hipFree(d->boff);
     (void)hipFree(d->dbof);
     (void)hipFree(d->loc);
@@ -998,7 +1070,17 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
         }
     }
     // deflation-block tables (lexicographic order of the deflation-block grid)
-    std::vector<int> boff((size_t)Nb * r), dbof(g.Nb), bnbr((size_t)Nb * 9);
+    std::vector<int> boff((size_t)Nb * r), dbof(g.Nb), bnbr((size_t)Nb * 9), brow;
+    brow.reserve(Nb);
+    for (int colour = 0; colour < 2; ++colour)
+        for (int B = 0; B < Nb; ++B) {
+            int q = B, sum = 0;
+            for (int m = 3; m >= 0; --m) {
+                sum += q % dg.nb[m];
+                q /= dg.nb[m];
+            }
+            if ((sum & 1) == colour) brow.push_back(B);
+        }
     for (int B = 0; B < Nb; ++B) {
         int c[4], q = B;
         for (int m = 3; m >= 0; --m) {
@@ -1034,6 +1116,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     DALLOC(d->A, sizeof(double2) * (size_t)Nb * 9 * Ns * Ns);
     DALLOC(d->Dinv, sizeof(double2) * (size_t)Nb * Ns * Ns);
     DALLOC(d->bnbr, sizeof(int) * (size_t)Nb * 9);
+    DALLOC(d->brow, sizeof(int) * (size_t)Nb);
     DALLOC(d->boff, sizeof(int) * (size_t)Nb * r);
     DALLOC(d->dbof, sizeof(int) * (size_t)g.Nb);
     DALLOC(d->loc, sizeof(int) * V);
@@ -1046,6 +1129,7 @@ int deflation_setup(qcd_field f, const qcd_dfl_params *prm, hipStream_t s, qcd_d
     hipError_t e = hipMemcpyAsync(d->bnbr, bnbr.data(), sizeof(int) * bnbr.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d->boff, boff.data(), sizeof(int) * boff.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d->dbof, dbof.data(), sizeof(int) * dbof.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->brow, brow.data(), sizeof(int) * brow.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         k_block_site_tables<<<nblocks(V, 256), 256, 0, s>>>(dg, f->lex_of, d->loc, d->blex);
         e = hipGetLastError();

@@ -16,6 +16,7 @@ struct qcd_dfl_s {
     double2 *A = nullptr;      // little operator [Nb][9][Ns][Ns], d = 0 self, 1+2mu+dir neighbours
     double2 *Dinv = nullptr;   // inverse diagonal blocks [Nb][Ns][Ns]
     int *bnbr = nullptr;       // [Nb][9] neighbour deflation block (lexicographic), d as for A
+    int *brow = nullptr;       // [Nb] deflation blocks by colour: the Nb/2 even ones, then the odd ones
     int *boff = nullptr;       // [Nb][r] internal site offset (rank * Vbh) of each member Schwarz block
     int *dbof = nullptr;       // [Schwarz blocks] deflation block of the Schwarz block of memory rank k
     int *loc = nullptr;        // [V] internal site -> lexicographic site index inside its deflation block
