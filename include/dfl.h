@@ -308,7 +308,7 @@ int ama_solve_multi(int nfield, const qcd_field *fields, const qcd_ama *sets, vo
  * into a HIP graph (on a stream the handle owns) and replayed for every
  * later batch of that size, on `stream`.  Little solves inside then run
  * a fixed budget: p->little_maxit iterations in P_R, and one cycle of
- * max(24, p->little_maxit) iterations in the low-mode correction.
+ * max(12, p->little_maxit) iterations in the low-mode correction.
  * info[r].rel_res is the FP64 relative residual after the fixed
  * iterations; status QCD_NOCONV if it is above p->res.  Graphs are kept in the handle until a workspace buffer
  * grows or the handle is destroyed.  Calls must not overlap in time with

@@ -9,7 +9,7 @@ constexpr int BLAS_NBLK = 512;  // maximum workgroups per right-hand side (parti
 constexpr int NKV_MAX = 32;     // Krylov vectors per cycle
 // little-solve iterations of the low-mode correction in solves without
 // host synchronisation (one cycle of the little GCR)
-constexpr int LOW_MODE_FIXED_ITERS = 24;
+constexpr int LOW_MODE_FIXED_ITERS = 12;
 
 // Reduced sums land in `out` ([n][nv] doubles); `part` needs n * nv * BLAS_NBLK doubles.
 int blas_reduce(const double *part, int nv, int nblk, int n, double *out, hipStream_t s);

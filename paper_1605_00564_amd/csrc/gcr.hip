@@ -120,10 +120,10 @@ int gcr_run(qcd_field f, const qcd_gcr *p, const double2 *b, double2 *x, int n, 
     if constexpr (std::is_same_v<E, float4>) rho32 = rho;
     bool rho_ready = false;
     auto low_mode_correction = [&]() -> int {
-        // without host polls the correction's little solve runs one whole
-        // Krylov cycle (24 iterations, or little_maxit if larger): the
-        // block-Jacobi little GCR reaches about 1e-7 there on 4^4 blocks,
-        // where the P_R budget of a few iterations would leave ~1e-2
+        // without host polls the correction's little solve runs one
+        // Krylov cycle of 12 iterations (or little_maxit if larger): the
+        // Schur-complement little GCR reaches about 1e-8 there on 4^4
+        // blocks, where the P_R budget of a few iterations leaves ~1e-3
         DFL_TRY(dfl_low_mode(p->dfl, x_zero ? b : r, x, n, p->little_tol,
                              ns ? std::max(p->little_maxit, LOW_MODE_FIXED_ITERS) : std::max(p->little_maxit, 200),
                              x_zero, s));
