@@ -15,7 +15,11 @@
 // block's update its residual equals the final minimal-residual vector on
 // the block's even sites, and rho_o + kappa H_oe x_e - A_oo delta_o on its
 // odd sites (zero when the stored inverse clover is the exact inverse of the
-// stored clover; at FP16 storage it is not); both are stored (`res`).  Until the
+// stored clover; at FP16 storage it is not); both are stored (`res`).  Within
+// a sweep the block's rho_o waits in its own odd sites of `res` while the
+// MinRes steps use the LDS; the back substitution then forms
+// u_o = rho_o + kappa H_oe x_e, delta_o = A_oo^{-1} u_o and the odd residual
+// from it, so s_o = A_oo^{-1} rho_o (needed for rhat_e) is never stored.  Until the
 // block is visited again only the blocks of the other colour change, by
 // their corrections delta (stored in `dlt` by every sweep), and they enter
 // the block's residual only through the hops that cross its faces:
@@ -182,7 +186,8 @@ __global__ void __launch_bounds__(MAXT)
         face_round<S, R, LF, 3>(bface, fcap, nface.w, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
         __syncthreads();
     }
-    // ---- s_o = A_oo^{-1} rho_o into T (rho_o kept for the odd residual) ----
+    // ---- s_o = A_oo^{-1} rho_o into T; rho_o is parked in the residual
+    //      buffer for the back substitution (this block's odd sites only) ----
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
@@ -190,41 +195,24 @@ __global__ void __launch_bounds__(MAXT)
             cx<R> e[12], m[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) e[c] = Tb[c * Vbh + j];
-            if (flags & SW_STORE_RES) Spin<S>::store(res, V, Vh + boff + j + qoff, e);
+            Spin<S>::store(res, V, Vh + boff + j + qoff, e);
             clover_apply<CF>(cinv, Vh, boff + j, e, m);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = m[c];
         }
     }
     __syncthreads();
-    // ---- r = rhat_e = rho_e + kappa H_eo s_o ; x_e = 0 ; s_o kept (psi_o or
-    //      the stored correction) ----
-    // (the neighbour blocks' corrections were read before the barriers above,
-    //  and no other workgroup of this colour touches this block)
+    // ---- r = rhat_e = rho_e + kappa H_eo s_o ; x_e = 0 ----
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
         if (j < Vbh) {
-            cx<R> acc[12], q[12];
+            cx<R> acc[12];
             block_hop<R, LF, false>(U, lnbr, V, Vh, boff, j, Vbh, Tb, acc);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 Rb[c * Vbh + j] = rmac(Rb[c * Vbh + j], kappa, acc[c]);
                 xe[k][c] = {R(0), R(0)};
-            }
-            const long xo_i = Vh + boff + j;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) q[c] = Tb[c * Vbh + j];
-            if (keep_dlt) {
-                // delta_o = s_o + kappa A^-1 H_oe x_e is completed at the end
-                Spin<S>::store(dlt, V, xo_i + qoff, q);
-            } else {
-                if (!first) {
-                    Spin<S>::load(psi, V, xo_i + qoff, acc);   // acc is no longer needed
-#pragma unroll
-                    for (int c = 0; c < 12; ++c) q[c] = q[c] + acc[c];
-                }
-                Spin<S>::store(psi, V, xo_i + qoff, q);
             }
         }
     }
@@ -323,7 +311,10 @@ __global__ void __launch_bounds__(MAXT)
         }
         __syncthreads();
     }
-    // ---- delta_o = s_o + kappa A_oo^{-1} H_oe x_e, delta_e = x_e; psi += delta ----
+    // ---- u_o = rho_o + kappa H_oe x_e, delta_o = A_oo^{-1} u_o, delta_e = x_e;
+    //      psi += delta ----
+    // (the neighbour blocks' corrections were read before the barriers above,
+    //  and no other workgroup of this colour touches this block)
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int j = tid + k * NT;
@@ -331,32 +322,26 @@ __global__ void __launch_bounds__(MAXT)
             const long xe_i = boff + j, xo_i = Vh + boff + j;
             cx<R> acc[12], t[12], q[12];
             block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
-            clover_apply<CF>(cinv, Vh, boff + j, acc, t);
-            if (keep_dlt) {
-                Spin<S>::load(dlt, V, xo_i + qoff, q);
+            Spin<S>::load(res, V, xo_i + qoff, t);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);   // delta_o
+            for (int c = 0; c < 12; ++c) acc[c] = rmac(t[c], kappa, acc[c]);   // u_o
+            clover_apply<CF>(cinv, Vh, boff + j, acc, q);                       // delta_o
+            if (keep_dlt) {
                 Spin<S>::store(dlt, V, xo_i + qoff, q);
                 Spin<S>::store(dlt, V, xe_i + qoff, xe[k]);
-                if (flags & SW_STORE_RES) {
-                    // odd residual rho_o + kappa H_oe x_e - A_oo delta_o (the
-                    // correction is kept whenever the residual is)
-                    clover_apply<CF>(clo, V, xo_i, q, t);
-                    cx<R> r[12];
-                    Spin<S>::load(res, V, xo_i + qoff, r);
+            }
+            if (flags & SW_STORE_RES) {
+                // odd residual u_o - A_oo delta_o: zero up to rounding when the
+                // stored inverse is exact, the stored inverse's defect otherwise
+                clover_apply<CF>(clo, V, xo_i, q, t);
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) r[c] = rmac(r[c], kappa, acc[c]) - t[c];
-                    Spin<S>::store(res, V, xo_i + qoff, r);
-                }
-                if (!first) {
-                    Spin<S>::load(psi, V, xo_i + qoff, t);
+                for (int c = 0; c < 12; ++c) t[c] = acc[c] - t[c];
+                Spin<S>::store(res, V, xo_i + qoff, t);
+            }
+            if (!first) {
+                Spin<S>::load(psi, V, xo_i + qoff, t);
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) q[c] = q[c] + t[c];
-                }
-            } else {
-                Spin<S>::load(psi, V, xo_i + qoff, q);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = rmac(q[c], kappa, t[c]);
+                for (int c = 0; c < 12; ++c) q[c] = q[c] + t[c];
             }
             Spin<S>::store(psi, V, xo_i + qoff, q);
             if (first) {
