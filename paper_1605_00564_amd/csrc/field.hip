@@ -766,7 +766,37 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
     }
     std::vector<int> fl((size_t)4 * f->face_cap, 0);
     for (int mu = 0; mu < 4; ++mu) std::copy(face[mu].begin(), face[mu].end(), fl.begin() + (size_t)mu * f->face_cap);
-    if (!dev_alloc(f->device, (void **)&f->bface, sizeof(int) * fl.size()))
+    // the source of each face entry: x on the forward face (d = 0) is fed by
+    // x + mu, the site with c_mu = 0 in the next block; x on the backward
+    // face by x - mu, the site with c_mu = b_mu - 1 in the previous block
+    std::vector<int> fsrc((size_t)4 * f->face_cap, 0);
+    f->nface_tot = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        f->nface_tot += f->nface[mu];
+        for (int k = 0; k < f->nface[mu]; ++k) {
+            const int ent = face[mu][k], par = ent >> 30, d = (ent >> 29) & 1, j = ent & 0x1fffffff;
+            int c[4], l = -1;
+            for (int cand = 2 * j; cand <= 2 * j + 1 && l < 0; ++cand) {
+                int r = cand, sum = 0;
+                for (int m = 3; m >= 0; --m) {
+                    c[m] = r % g.b[m];
+                    r /= g.b[m];
+                    sum += c[m];
+                }
+                if ((sum & 1) == par) l = cand;
+            }
+            c[mu] = d == 0 ? 0 : g.b[mu] - 1;
+            int l2 = 0, sum = 0;
+            for (int m = 0; m < 4; ++m) {
+                l2 = l2 * g.b[m] + c[m];
+                sum += c[m];
+            }
+            fsrc[(size_t)mu * f->face_cap + k] = ((sum & 1) << 30) | (l2 >> 1);
+        }
+    }
+    if (!dev_alloc(f->device, (void **)&f->bface, sizeof(int) * fl.size()) ||
+        !dev_alloc(f->device, (void **)&f->bfsrc, sizeof(int) * fsrc.size()) ||
+        !dev_alloc(f->device, (void **)&f->bfnb, sizeof(int) * 8 * (size_t)g.Nb))
         return fail(set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create"));
     // stencil launch defaults, overridable from the environment
     if (const char *e = getenv("DFL_STENCIL_BLOCK")) f->st_block = atoi(e);
@@ -788,8 +818,31 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         }
         bord[Bl] = (bsum & 1) * (g.Nb / 2) + Bl / 2;
     }
+    // block neighbours for the face exchange of the Schwarz sweeps
+    std::vector<int> fnb((size_t)8 * g.Nb);
+    for (int Bl = 0; Bl < g.Nb; ++Bl) {
+        int cb[4], r = Bl;
+        for (int m = 3; m >= 0; --m) {
+            cb[m] = r % g.nb[m];
+            r /= g.nb[m];
+        }
+        for (int mu = 0; mu < 4; ++mu)
+            for (int d = 0; d < 2; ++d) {
+                int cc[4] = {cb[0], cb[1], cb[2], cb[3]};
+                cc[mu] = (cc[mu] + (d == 0 ? -1 : 1) + g.nb[mu]) % g.nb[mu];
+                int Rl = 0;
+                for (int m = 0; m < 4; ++m) Rl = Rl * g.nb[m] + cc[m];
+                // d = 0: the reader's forward face meets this block's first
+                // time slice; d = 1: its backward face meets the last one
+                const bool wrap = mu == 0 && (d == 0 ? cb[0] == 0 : cb[0] == g.nb[0] - 1);
+                fnb[(size_t)bord[Bl] * 8 + 2 * mu + d] =
+                    bord[Rl] | ((wrap && lat->bc_t == -1) ? (int)0x80000000u : 0);
+            }
+    }
     hipError_t e = hipMemcpyAsync(f->lnbr, lnb.data(), sizeof(short) * lnb.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(f->bface, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->bfsrc, fsrc.data(), sizeof(int) * fsrc.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->bfnb, fnb.data(), sizeof(int) * fnb.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(f->border, bord.data(), sizeof(int) * bord.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
@@ -848,6 +901,8 @@ int qcd_field_destroy(qcd_field f) {
     (void)hipFree(f->nbr);
     (void)hipFree(f->lnbr);
     (void)hipFree(f->bface);
+    (void)hipFree(f->bfsrc);
+    (void)hipFree(f->bfnb);
     (void)hipFree(f->border);
     (void)hipFree(f->int_of);
     (void)hipFree(f->lex_of);

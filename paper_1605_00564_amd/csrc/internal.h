@@ -606,6 +606,15 @@ struct qcd_field_s {
     int *bface = nullptr;
     int nface[4] = {0, 0, 0, 0};
     int face_cap = 0;
+    // per entry of bface: the site across the face, in the neighbouring
+    // block, that feeds it (parity << 30 | j); [4][face_cap]
+    int *bfsrc = nullptr;
+    // [Nb][8], block B (memory order) and entry kind 2 mu + d (d of bface):
+    // the block whose face entries of that kind B feeds (B - mu for d = 0,
+    // B + mu for d = 1), in memory order; bit 31: the hop crosses the
+    // antiperiodic time boundary
+    int *bfnb = nullptr;
+    int nface_tot = 0;       // sum of nface: face entries per block
     int *int_of = nullptr;   // [V] lexicographic -> internal
     int *lex_of = nullptr;   // [V] internal -> lexicographic
     int *border = nullptr;   // [Nb] lexicographic block -> block index in memory (colour-major)

@@ -19,11 +19,15 @@
 // a sweep the block's rho_o waits in its own odd sites of `res` while the
 // MinRes steps use the LDS; the back substitution then forms
 // u_o = rho_o + kappa H_oe x_e, delta_o = A_oo^{-1} u_o and the odd residual
-// from it, so s_o = A_oo^{-1} rho_o (needed for rhat_e) is never stored.  Until the
-// block is visited again only the blocks of the other colour change, by
-// their corrections delta (stored in `dlt` by every sweep), and they enter
-// the block's residual only through the hops that cross its faces:
+// from it, so s_o = A_oo^{-1} rho_o (needed for rhat_e) is never stored.
+// Until the block is visited again only the blocks of the other colour
+// change, by their corrections delta, and they enter the block's residual
+// only through the hops that cross its faces:
 //     rho_block = res_block + kappa H_{block <- neighbours} delta.
+// Each sweep but the last hands those hops over ready-made: a block ends by
+// writing, for every face site of its neighbours, the link times the spin
+// projection of its delta (a half-spinor), in the order of the neighbour's
+// face table, so the neighbour's next sweep reads them contiguously.
 // The first cycle starts from rho = eta (psi = 0).  The face hops of a block
 // are listed per direction mu (block-face table, the same for every block):
 // all threads of the workgroup take one direction per round, so no two of
@@ -78,37 +82,116 @@ __device__ inline void block_hop(const void *U, const short *lnbr, long V, long 
 #undef DFL_BHOP
 }
 
-// kappa times the hops into the block across one face direction MU of the
-// block, from the corrections of the neighbouring blocks, added to the LDS
-// (or global) exchange buffers: entry (parity, fwd/bwd, j) of the face table
-template <class S, class R, int LF, int MU>
-__device__ inline void face_round(const int *bface, int fcap, int nf, int tid, int NT, const void *U, const int *nbr,
-                                  const void *dlt, unsigned qoff, long V, long Vh, long boff, int Vbh, R kappa,
-                                  cx<R> *Rb, cx<R> *Tb) {
+// Half-spinor storage of the face exchange: the spin-projected, link-
+// multiplied hop (two colour vectors, 6 complex) in 16-byte chunks,
+// structure-of-arrays [chunk][n].
+template <class S>
+struct Half;
+template <>
+struct Half<double> {
+    static constexpr int NCH = 6;
+    template <class R>
+    __device__ static inline void load(const void *base, long n, unsigned idx, cx<R> v[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double2 t = ld<double2>(base, k, n, idx);
+            v[k] = {R(t.x), R(t.y)};
+        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long n, unsigned idx, const cx<R> v[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st<double2>(base, k, n, idx, make_double2(double(v[k].re), double(v[k].im)));
+    }
+};
+template <>
+struct Half<float> {
+    static constexpr int NCH = 3;
+    template <class R>
+    __device__ static inline void load(const void *base, long n, unsigned idx, cx<R> v[6]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float4 t = ld<float4>(base, c, n, idx);
+            v[2 * c] = {R(t.x), R(t.y)};
+            v[2 * c + 1] = {R(t.z), R(t.w)};
+        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long n, unsigned idx, const cx<R> v[6]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            st<float4>(base, c, n, idx,
+                       make_float4(float(v[2 * c].re), float(v[2 * c].im), float(v[2 * c + 1].re),
+                                   float(v[2 * c + 1].im)));
+    }
+};
+
+// Face exchange.  Entry k of direction MU of block B's face table (site x of
+// B, forward (d = 0) or backward (d = 1) face) receives the hop from the site
+// y = x +- mu of the neighbouring block N that swept last:
+//     d = 0: sign U_mu(x) (1 - gamma_mu) delta(y),
+//     d = 1: sign U_mu(y)^+ (1 + gamma_mu) delta(y),
+// as a half-spinor (the spin projection times the link).  N writes it at
+// the end of its sweep into slot (B, MU, k) of the exchange buffer (face_emit),
+// so that B's next sweep reads its face entries in table order, contiguous,
+// and only rebuilds the four spin components and scales by kappa
+// (face_absorb).  Slots: [rhs][chunk][block][sum of the face table lengths],
+// direction MU at offset fo (the lengths before it).
+template <class S, class R, int MU>
+__device__ inline void face_absorb(const int *bface, int fcap, int nf, int fo, int nft, int tid, int NT,
+                                   const void *fx, unsigned qoff, long nfx, long B, int Vbh, R kappa, cx<R> *Rb,
+                                   cx<R> *Tb) {
     for (int k = tid; k < nf; k += NT) {
         const int ent = bface[MU * fcap + k];
         const int par = ent >> 30, bwd = (ent >> 29) & 1, j = ent & 0x1fffffff;
-        const unsigned x = (unsigned)(par * Vh + boff + j);
-        cx<R> w[9], p[12], acc[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
-        const int e = nbr_at(nbr, 2 * MU + bwd, V, x);
-        const unsigned y = nb_index(e);
-        Spin<S>::load(dlt, V, y + qoff, p);
-        if (!bwd) {
-            Link<LF>::load(U, V, MU, x, w);
-            hop<R, MU, true>(w, p, nb_sign<R>(e), acc);
-        } else {
-            Link<LF>::load(U, V, MU, y, w);
-            hop<R, MU, false>(w, p, nb_sign<R>(e), acc);
-        }
+        cx<R> g[6], a[12];
+        Half<S>::load(fx, nfx, (unsigned)(B * nft + fo + k) + qoff, g);
         cx<R> *buf = par ? Tb : Rb;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) buf[c * Vbh + j] = rmac(buf[c * Vbh + j], kappa, acc[c]);
+        for (int c = 0; c < 12; ++c) a[c] = buf[c * Vbh + j];
+        if (!bwd)
+            reconstruct_add<R, MU, -1>(g, kappa, a);
+        else
+            reconstruct_add<R, MU, +1>(g, kappa, a);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) buf[c * Vbh + j] = a[c];
     }
 }
 
-enum SweepFlags { SW_FIRST = 1, SW_FACES = 2, SW_STORE_RES = 4, SW_STORE_DLT = 8 };
+// The hops of this block's correction (delta_e in De, delta_o in Do, local
+// index) into the face entries of its neighbours, for direction MU.
+template <class S, class R, int LF, int MU>
+__device__ inline void face_emit(const int *bface, const int *bfsrc, const int *bfnb, int fcap, int nf, int fo,
+                                 int nft, int tid, int NT, const void *U, void *fx, unsigned qoff, long nfx, long V,
+                                 long Vh, long B, int Vbh, const cx<R> *De, const cx<R> *Do) {
+    for (int k = tid; k < nf; k += NT) {
+        const int ent = bface[MU * fcap + k], src = bfsrc[MU * fcap + k];
+        const int par = ent >> 30, bwd = (ent >> 29) & 1, j = ent & 0x1fffffff;
+        const int py = src >> 30, jy = src & 0x3fffffff;
+        const int nb = bfnb[B * 8 + 2 * MU + bwd];
+        const long Rblk = nb & 0x7fffffff;
+        const cx<R> *buf = py ? Do : De;
+        cx<R> d[12], h[6], g[6], w[9];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) d[c] = buf[c * Vbh + jy];
+        if (!bwd) {
+            Link<LF>::load(U, V, MU, (unsigned)(par * Vh + Rblk * Vbh + j), w);
+            project<R, MU, -1>(d, h);
+            su3_mul2<R, false>(w, h, g);
+        } else {
+            Link<LF>::load(U, V, MU, (unsigned)(py * Vh + B * Vbh + jy), w);
+            project<R, MU, +1>(d, h);
+            su3_mul2<R, true>(w, h, g);
+        }
+        if (nb < 0) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) g[c] = {-g[c].re, -g[c].im};
+        }
+        Half<S>::store(fx, nfx, (unsigned)(Rblk * nft + fo + k) + qoff, g);
+    }
+}
+
+enum SweepFlags { SW_FIRST = 1, SW_FACES = 2, SW_STORE_RES = 4, SW_EMIT = 8 };
 
 // VBHC > 0: the block's sites per parity as a compile-time constant (the
 // component planes of the exchange buffers then sit at immediate LDS
@@ -120,15 +203,16 @@ enum SweepFlags { SW_FIRST = 1, SW_FACES = 2, SW_STORE_RES = 4, SW_STORE_DLT = 8
 // stay wave-uniform and a lane's right-hand side enters through its element
 // index (qr x NCH x V chunks further).
 template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0, int NR = 1>
-__global__ void __launch_bounds__(MAXT)
+__global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS && MAXT == 256 && VBHC > 0) ? 3 : 1)
     k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, void *__restrict__ res_all,
-                void *__restrict__ dlt_all, const void *__restrict__ U, const void *__restrict__ clo,
-                const void *__restrict__ cinv, const int *__restrict__ nbr, const short *__restrict__ lnbr,
-                const int *__restrict__ bface, int fcap, int4 nface, long V, long Vh, int Vbh_arg, int nbc, int colour,
-                R kappa, int nmr, int flags, cx<R> *gbuf) {
+                void *__restrict__ fx_all, const void *__restrict__ U, const void *__restrict__ clo,
+                const void *__restrict__ cinv, const short *__restrict__ lnbr, const int *__restrict__ bface,
+                const int *__restrict__ bfsrc, const int *__restrict__ bfnb, int fcap, int4 nface, long V, long Vh,
+                int Vbh_arg, int nbc, int colour, R kappa, int nmr, int flags, cx<R> *gbuf) {
     // flags: SW_FIRST: first cycle (rho starts from eta, psi is zero on this
-    // colour); SW_FACES: add the neighbours' corrections across the faces;
-    // SW_STORE_RES: keep the even-site residual; SW_STORE_DLT: keep the correction
+    // colour); SW_FACES: add the neighbours' hops across the faces;
+    // SW_STORE_RES: keep the block residual; SW_EMIT: write this block's hops
+    // into the neighbours' face entries
     static_assert(NR == 1 || (LDS && KS == 1 && Spin<S>::NCH * 16 == Spin<S>::BYTES), "NR = 2 layout");
     constexpr int SPW = 64 / NR;   // sites per wave
     const int Vbh = VBHC > 0 ? VBHC : Vbh_arg;
@@ -143,10 +227,14 @@ __global__ void __launch_bounds__(MAXT)
     const size_t fs = (size_t)Spin<S>::BYTES * V;
     const void *eta = wave_uniform(static_cast<const char *>(eta_all) + (size_t)rg * NR * fs);
     void *psi = wave_uniform(static_cast<char *>(psi_all) + (size_t)rg * NR * fs);
-    void *dlt = wave_uniform(static_cast<char *>(dlt_all) + (size_t)rg * NR * fs);
     void *res = wave_uniform(static_cast<char *>(res_all) + (size_t)rg * NR * fs);
     const unsigned qoff = (unsigned)(qr * Spin<S>::NCH * V);    // its offset, in chunks
-    const bool first = flags & SW_FIRST, keep_dlt = flags & SW_STORE_DLT;
+    // face exchange: nft entries per block, nfx per chunk plane
+    const int fo1 = nface.x, fo2 = fo1 + nface.y, fo3 = fo2 + nface.z, nft = fo3 + nface.w;
+    const long nfx = (long)nbc * 2 * nft;
+    void *fx = wave_uniform(static_cast<char *>(fx_all) + (size_t)rg * NR * Half<S>::NCH * 16 * nfx);
+    const unsigned qfx = (unsigned)(qr * Half<S>::NCH * nfx);
+    const bool first = flags & SW_FIRST;
     const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
     cx<R> *Rb, *Tb;
@@ -177,13 +265,13 @@ __global__ void __launch_bounds__(MAXT)
     }
     if (flags & SW_FACES) {
         __syncthreads();
-        face_round<S, R, LF, 0>(bface, fcap, nface.x, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        face_absorb<S, R, 0>(bface, fcap, nface.x, 0, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_round<S, R, LF, 1>(bface, fcap, nface.y, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        face_absorb<S, R, 1>(bface, fcap, nface.y, fo1, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_round<S, R, LF, 2>(bface, fcap, nface.z, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        face_absorb<S, R, 2>(bface, fcap, nface.z, fo2, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_round<S, R, LF, 3>(bface, fcap, nface.w, tid, NT, U, nbr, dlt, qoff, V, Vh, boff, Vbh, kappa, Rb, Tb);
+        face_absorb<S, R, 3>(bface, fcap, nface.w, fo3, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
     }
     // ---- s_o = A_oo^{-1} rho_o into T; rho_o is parked in the residual
@@ -326,9 +414,10 @@ __global__ void __launch_bounds__(MAXT)
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = rmac(t[c], kappa, acc[c]);   // u_o
             clover_apply<CF>(cinv, Vh, boff + j, acc, q);                       // delta_o
-            if (keep_dlt) {
-                Spin<S>::store(dlt, V, xo_i + qoff, q);
-                Spin<S>::store(dlt, V, xe_i + qoff, xe[k]);
+            if (flags & SW_EMIT) {
+                // delta_o for the face exchange (T is free: only R = x_e is read here)
+#pragma unroll
+                for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = q[c];
             }
             if (flags & SW_STORE_RES) {
                 // odd residual u_o - A_oo delta_o: zero up to rounding when the
@@ -354,6 +443,17 @@ __global__ void __launch_bounds__(MAXT)
             }
         }
     }
+    if (flags & SW_EMIT) {
+        __syncthreads();
+        face_emit<S, R, LF, 0>(bface, bfsrc, bfnb, fcap, nface.x, 0, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh, Rb,
+                               Tb);
+        face_emit<S, R, LF, 1>(bface, bfsrc, bfnb, fcap, nface.y, fo1, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+                               Rb, Tb);
+        face_emit<S, R, LF, 2>(bface, bfsrc, bfnb, fcap, nface.z, fo2, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+                               Rb, Tb);
+        face_emit<S, R, LF, 3>(bface, bfsrc, bfnb, fcap, nface.w, fo3, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+                               Rb, Tb);
+    }
 }
 
 template <class S, class R, int LF, int CF>
@@ -376,11 +476,12 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
         DFL_TRY(field_buffer(f, BUF_SAP, (size_t)nbc * nrhs * lds, &p));
         gbuf = static_cast<cx<R> *>(p);
     }
-    // the blocks' stored even-site residuals and the last sweep's corrections
+    // the blocks' stored residuals and the face exchange (half-spinors)
     void *rp;
-    const size_t rbytes = (size_t)Spin<S>::BYTES * g.V * nrhs, dbytes = rbytes;
-    DFL_TRY(field_buffer(f, BUF_SAP_RES, rbytes + dbytes, &rp));
-    void *res = rp, *dlt = static_cast<char *>(rp) + rbytes;
+    const size_t rbytes = (size_t)Spin<S>::BYTES * g.V * nrhs;
+    const size_t xbytes = (size_t)Half<S>::NCH * 16 * g.Nb * f->nface_tot * nrhs;
+    DFL_TRY(field_buffer(f, BUF_SAP_RES, rbytes + xbytes, &rp));
+    void *res = rp, *fx = static_cast<char *>(rp) + rbytes;
     const R kappa = (R)f->lat.kappa;
     const int4 nface = make_int4(f->nface[0], f->nface[1], f->nface[2], f->nface[3]);
     const bool pair = sizeof(S) == 4 && f->st_sap_pair && use_lds && Vbh == 128 && NT == 128 && nrhs % 2 == 0;
@@ -388,13 +489,14 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     // colour, with h = 165 flop per hop times the hops that stay inside the
     // block (sum over mu of 2 (b_mu - 1) / b_mu per site) and nf the hops
     // that cross the block's faces per pair (sum over mu of 4 / b_mu):
-    //   neighbours' corrections nf (165 + 24) (not in the first sweep),
+    //   the neighbours' hops across the faces nf 48 (not in the first sweep),
     //   s_o = A^-1 rho_o 504, rhat_e h + 72, each MinRes step 2h + 1392,
-    //   back substitution and correction h + 576, odd residual 552 (when kept).
+    //   back substitution and correction h + 576, odd residual 552 (when kept),
+    //   this block's hops into the neighbours' faces nf 144 (but the last sweep).
     // Compulsory bytes per pair: eta (first cycle) or the stored residual,
-    // the neighbours' corrections across the faces, psi in (after the first
-    // cycle) and out, the stored residual and correction out; 4 links and the
-    // clover term per site, the inverse clover per odd site.
+    // the face half-spinors in (nf B / 2), psi in (after the first cycle) and
+    // out, the stored residual out, the face half-spinors out (nf B / 2); 4
+    // links and the clover term per site, the inverse clover per odd site.
     double hops = 0, nf = 0;
     for (int m = 0; m < 4; ++m) {
         hops += 2.0 * (g.b[m] - 1) / g.b[m];
@@ -410,17 +512,18 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
             if (cy == 0) flags |= SW_FIRST;
             if (cy > 0 || col == 1) flags |= SW_FACES;
             if (cy + 1 < ncy) flags |= SW_STORE_RES;
-            if (!(cy + 1 == ncy && col == 1)) flags |= SW_STORE_DLT;
+            if (!(cy + 1 == ncy && col == 1)) flags |= SW_EMIT;
             dim3 grid(nbc, nrhs);
-            const double fl = pairs * (((flags & SW_FACES) ? nf * 189.0 : 0.0) + 504 + (h + 72) +
-                                       nmr * (2 * h + 1392) + (h + 576) + ((flags & SW_STORE_RES) ? 552 : 0));
-            const double by = pairs * (B * (2 + ((flags & SW_FACES) ? nf : 0) + (cy == 0 ? 2 : 4) +
-                                            ((flags & SW_STORE_RES) ? 2 : 0) + ((flags & SW_STORE_DLT) ? 2 : 0))) +
+            const double fl = pairs * (((flags & SW_FACES) ? nf * 48.0 : 0.0) + 504 + (h + 72) +
+                                       nmr * (2 * h + 1392) + (h + 576) + ((flags & SW_STORE_RES) ? 552 : 0) +
+                                       ((flags & SW_EMIT) ? nf * 144.0 : 0.0));
+            const double by = pairs * (B * (2 + ((flags & SW_FACES) ? nf / 2 : 0) + (cy == 0 ? 2 : 4) +
+                                            ((flags & SW_STORE_RES) ? 2 : 0) + ((flags & SW_EMIT) ? nf / 2 : 0))) +
                               (double)nbc * Vbh * 2 * (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
             ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
 #define DFL_SAP_ARGS                                                                                             \
-    eta, psi, res, dlt, f->U[LF], f->clo[CF], f->cloinv[CF], f->nbr, f->lnbr, f->bface, f->face_cap, nface, g.V, \
-        g.Vh, Vbh, nbc, col, kappa, nmr, flags, gbuf
+    eta, psi, res, fx, f->U[LF], f->clo[CF], f->cloinv[CF], f->lnbr, f->bface, f->bfsrc, f->bfnb, f->face_cap, \
+        nface, g.V, g.Vh, Vbh, nbc, col, kappa, nmr, flags, gbuf
 #define DFL_SAP_LAUNCH(LDSV, KSV, MAXT, VBHC)                                                                  \
     {                                                                                                          \
         auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT, VBHC>;                                          \
