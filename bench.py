@@ -619,6 +619,9 @@ def main():
     ap.add_argument("--sweep-block-ns", default="",
                     help="one AMA step per block shape and N_s, e.g. '4,4,4,4:8,12,20;8,4,4,4:8,12,20'")
     ap.add_argument("--sloppy-storage", type=int, default=F16)
+    ap.add_argument("--sloppy-vecs", type=int, default=F16,
+                    help="storage of the sloppy Schwarz sweeps' own vectors (2 = FP16, 1 = FP32; FP16 needs "
+                         "FP16/BF16 link storage)")
     ap.add_argument("--batch", type=int, default=24, help="right-hand sides per solver launch (0: from free memory)")
     ap.add_argument("--little-maxit", type=int, default=16,
                     help="little-solve iterations inside P_R for the exact solves")
@@ -692,7 +695,7 @@ def main():
     del U
     log(f"[bench] gauge field generated and uploaded in {time.perf_counter() - t:.1f} s")
 
-    sap_sloppy = dfl.SapParams(5, 4, args.sloppy_storage)
+    sap_sloppy = dfl.SapParams(5, 4, args.sloppy_storage, args.sloppy_vecs)
     sap_exact = dfl.SapParams(5, 4, F32)
     # sloppy solutions stored in FP32, exact ones in FP64
     xs = [torch.empty((12, V, 4, 3), dtype=torch.complex64, device="cuda") for _ in range(npos)]
@@ -834,7 +837,8 @@ def main():
                    "Ns": 0 if args.no_deflation else args.ns, "positions": npos,
                    "deflation_block": list(dblock or block), "nref": args.nref, "sloppy_rhs": 12 * npos,
                    "exact_rhs": 12, "sloppy_res": 3e-3, "exact_res": 1e-10,
-                   "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage], "ncy": 5, "nmr": 4,
+                   "sloppy_storage": ["f64", "f32", "f16", "bf16"][args.sloppy_storage],
+                   "sloppy_sap_vectors": ["f64", "f32", "f16", "bf16"][args.sloppy_vecs], "ncy": 5, "nmr": 4,
                    "little_maxit": {"sloppy": args.little_maxit_sloppy, "exact": args.little_maxit}},
         "roofline": roof,
         "stencil_roofline": stencil,

@@ -140,6 +140,11 @@ typedef struct {
     int ncy;           /* Schwarz cycles (the paper keeps 5) */
     int nmr;           /* minimal-residual steps per block solve */
     qcd_prec storage;  /* QCD_F64 (all FP64), QCD_F32, QCD_F16, QCD_BF16 (FP32 arithmetic) */
+    qcd_prec vecs;     /* storage of the sweeps' own vectors (the blocks' stored residuals
+                          and the half-spinors handed across block faces): QCD_F16 = FP16
+                          with a power-of-two scale per site (per face entry), allowed with
+                          F16/BF16 storage; any other value keeps the arithmetic precision.
+                          The input and the output keep the arithmetic precision. */
 } qcd_sap;
 
 int sap_precond(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, qcd_prec io,

@@ -40,7 +40,7 @@ class _Lattice(C.Structure):
 
 
 class _Sap(C.Structure):
-    _fields_ = [("ncy", C.c_int), ("nmr", C.c_int), ("storage", C.c_int)]
+    _fields_ = [("ncy", C.c_int), ("nmr", C.c_int), ("storage", C.c_int), ("vecs", C.c_int)]
 
 
 class _DflParams(C.Structure):
@@ -177,9 +177,10 @@ class SapParams:
     ncy: int = 5
     nmr: int = 4
     storage: int = F32
+    vecs: int = F32     # F16: the sweeps' stored residuals and face half-spinors in FP16
 
     def c(self):
-        return _Sap(self.ncy, self.nmr, self.storage)
+        return _Sap(self.ncy, self.nmr, self.storage, self.vecs)
 
 
 @dataclass

@@ -228,6 +228,17 @@ struct Spin<float> {
     }
 };
 
+// The power-of-two scale of an FP16 vector whose largest |re| or |im| is m:
+// m = f 2^e with f in [0.5, 1) (e = biased exponent - 126); the scale 2^(e-15)
+// and its inverse are built from exponent bits, and vectors whose largest
+// entry is below 2^-112 are stored as zero.
+__device__ inline void r16_scale(float m, float &sc, float &inv) {
+    const int eb = (int)((__float_as_uint(m) >> 23) & 0xffu);
+    const bool nz = eb >= 15;
+    sc = nz ? __uint_as_float((unsigned)(eb - 14) << 23) : 0.f;
+    inv = nz ? __uint_as_float((unsigned)(268 - eb) << 23) : 0.f;
+}
+
 // FP16 spinor with a per-site power-of-two scale: a right-hand side holds
 // 3 chunks of [V] x 8 halves (4 complex each), then [V] FP32 scales (52 V
 // bytes).  The scale 2^e puts the site's largest |re| or |im| in
@@ -253,27 +264,27 @@ struct Spin<__half> {
         decode(t, ld<float>(base, 12, V, idx), v);
     }
     template <class R>
-    __device__ static inline void store(void *base, long V, unsigned idx, const cx<R> v[12]) {
+    __device__ static inline void encode(const cx<R> v[12], h8 t[3], float &sc) {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(float(v[k].re)), fabsf(float(v[k].im))));
-        // m = f 2^e with f in [0.5, 1): e = biased exponent - 126.  Scale
-        // 2^(e-15) and its inverse are built from exponent bits; sites whose
-        // largest entry is below 2^-112 are stored as zero.
-        const int eb = (int)((__float_as_uint(m) >> 23) & 0xffu);
-        const bool nz = eb >= 15;
-        const float sc = nz ? __uint_as_float((unsigned)(eb - 14) << 23) : 0.f;
-        const float inv = nz ? __uint_as_float((unsigned)(268 - eb) << 23) : 0.f;
+        float inv;
+        r16_scale(m, sc, inv);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            h8 t;
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                t.v[2 * q] = __float2half_rn(float(v[4 * c + q].re) * inv);
-                t.v[2 * q + 1] = __float2half_rn(float(v[4 * c + q].im) * inv);
+                t[c].v[2 * q] = __float2half_rn(float(v[4 * c + q].re) * inv);
+                t[c].v[2 * q + 1] = __float2half_rn(float(v[4 * c + q].im) * inv);
             }
-            st<h8>(base, c, V, idx, t);
-        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long V, unsigned idx, const cx<R> v[12]) {
+        h8 t[3];
+        float sc;
+        encode(v, t, sc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st<h8>(base, c, V, idx, t[c]);
         st<float>(base, 12, V, idx, sc);
     }
 };

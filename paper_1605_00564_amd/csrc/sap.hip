@@ -82,16 +82,70 @@ __device__ inline void block_hop(const void *U, const short *lnbr, long V, long 
 #undef DFL_BHOP
 }
 
-// Half-spinor storage of the face exchange: the spin-projected, link-
-// multiplied hop (two colour vectors, 6 complex) in 16-byte chunks,
-// structure-of-arrays [chunk][n].
-template <class S>
-struct Half;
+// Storage of the sweep's own vectors: the block residuals (with the parked
+// rho_o) as full spinors, and the face exchange as half-spinors (the spin
+// projection times the link: two colour vectors, 6 complex).  Each type is a
+// structure-of-arrays per right-hand side, and q is the right-hand side's
+// place in the workgroup's pair (its data follow those of the first), so the
+// base stays the same in every lane.  FP16 keeps a power-of-two scale per
+// site (per face entry), after the 16-byte (8-byte) chunks.
+template <class SI>
+struct VecI;
 template <>
-struct Half<double> {
-    static constexpr int NCH = 6;
+struct VecI<double> {
+    static constexpr size_t BYTES = 192;
     template <class R>
-    __device__ static inline void load(const void *base, long n, unsigned idx, cx<R> v[6]) {
+    __device__ static inline void load(const void *b, long V, unsigned i, int q, cx<R> v[12]) {
+        Spin<double>::load(b, V, i + (unsigned)(q * 12 * V), v);
+    }
+    template <class R>
+    __device__ static inline void store(void *b, long V, unsigned i, int q, const cx<R> v[12]) {
+        Spin<double>::store(b, V, i + (unsigned)(q * 12 * V), v);
+    }
+};
+template <>
+struct VecI<float> {
+    static constexpr size_t BYTES = 96;
+    template <class R>
+    __device__ static inline void load(const void *b, long V, unsigned i, int q, cx<R> v[12]) {
+        Spin<float>::load(b, V, i + (unsigned)(q * 6 * V), v);
+    }
+    template <class R>
+    __device__ static inline void store(void *b, long V, unsigned i, int q, const cx<R> v[12]) {
+        Spin<float>::store(b, V, i + (unsigned)(q * 6 * V), v);
+    }
+};
+// 52 V bytes per right-hand side: V is a multiple of 16, so the second one
+// starts at a whole number of 16-byte (13 V / 4) and 4-byte (13 V) units
+template <>
+struct VecI<__half> {
+    static constexpr size_t BYTES = 52;
+    template <class R>
+    __device__ static inline void load(const void *b, long V, unsigned i, int q, cx<R> v[12]) {
+        h8 t[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t[c] = ld<h8>(b, c, V, i + (unsigned)(q * 13 * V / 4));
+        Spin<__half>::decode(t, ld<float>(b, 12, V, i + (unsigned)(q * 13 * V)), v);
+    }
+    template <class R>
+    __device__ static inline void store(void *b, long V, unsigned i, int q, const cx<R> v[12]) {
+        h8 t[3];
+        float sc;
+        Spin<__half>::encode(v, t, sc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st<h8>(b, c, V, i + (unsigned)(q * 13 * V / 4), t[c]);
+        st<float>(b, 12, V, i + (unsigned)(q * 13 * V), sc);
+    }
+};
+
+template <class SI>
+struct HalfI;
+template <>
+struct HalfI<double> {
+    static constexpr size_t BYTES = 96;
+    template <class R>
+    __device__ static inline void load(const void *base, long n, unsigned idx, int q, cx<R> v[6]) {
+        idx += (unsigned)(q * 6 * n);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const double2 t = ld<double2>(base, k, n, idx);
@@ -99,16 +153,18 @@ struct Half<double> {
         }
     }
     template <class R>
-    __device__ static inline void store(void *base, long n, unsigned idx, const cx<R> v[6]) {
+    __device__ static inline void store(void *base, long n, unsigned idx, int q, const cx<R> v[6]) {
+        idx += (unsigned)(q * 6 * n);
 #pragma unroll
         for (int k = 0; k < 6; ++k) st<double2>(base, k, n, idx, make_double2(double(v[k].re), double(v[k].im)));
     }
 };
 template <>
-struct Half<float> {
-    static constexpr int NCH = 3;
+struct HalfI<float> {
+    static constexpr size_t BYTES = 48;
     template <class R>
-    __device__ static inline void load(const void *base, long n, unsigned idx, cx<R> v[6]) {
+    __device__ static inline void load(const void *base, long n, unsigned idx, int q, cx<R> v[6]) {
+        idx += (unsigned)(q * 3 * n);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float4 t = ld<float4>(base, c, n, idx);
@@ -117,12 +173,47 @@ struct Half<float> {
         }
     }
     template <class R>
-    __device__ static inline void store(void *base, long n, unsigned idx, const cx<R> v[6]) {
+    __device__ static inline void store(void *base, long n, unsigned idx, int q, const cx<R> v[6]) {
+        idx += (unsigned)(q * 3 * n);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             st<float4>(base, c, n, idx,
                        make_float4(float(v[2 * c].re), float(v[2 * c].im), float(v[2 * c + 1].re),
                                    float(v[2 * c + 1].im)));
+    }
+};
+// 28 n bytes per right-hand side (3 chunks of 8 bytes, then the scales); n is
+// even, so the second one starts at 7 n / 2 eight-byte and 7 n four-byte units
+template <>
+struct HalfI<__half> {
+    static constexpr size_t BYTES = 28;
+    template <class R>
+    __device__ static inline void load(const void *base, long n, unsigned idx, int q, cx<R> v[6]) {
+        const float sc = ld<float>(base, 6, n, idx + (unsigned)(q * 7 * n));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const h4 t = ld<h4>(base, c, n, idx + (unsigned)(q * 7 * n / 2));
+            v[2 * c] = {R(__half2float(t.v[0]) * sc), R(__half2float(t.v[1]) * sc)};
+            v[2 * c + 1] = {R(__half2float(t.v[2]) * sc), R(__half2float(t.v[3]) * sc)};
+        }
+    }
+    template <class R>
+    __device__ static inline void store(void *base, long n, unsigned idx, int q, const cx<R> v[6]) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m = fmaxf(m, fmaxf(fabsf(float(v[k].re)), fabsf(float(v[k].im))));
+        float sc, inv;
+        r16_scale(m, sc, inv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h4 t;
+            t.v[0] = __float2half_rn(float(v[2 * c].re) * inv);
+            t.v[1] = __float2half_rn(float(v[2 * c].im) * inv);
+            t.v[2] = __float2half_rn(float(v[2 * c + 1].re) * inv);
+            t.v[3] = __float2half_rn(float(v[2 * c + 1].im) * inv);
+            st<h4>(base, c, n, idx + (unsigned)(q * 7 * n / 2), t);
+        }
+        st<float>(base, 6, n, idx + (unsigned)(q * 7 * n), sc);
     }
 };
 
@@ -137,15 +228,15 @@ struct Half<float> {
 // and only rebuilds the four spin components and scales by kappa
 // (face_absorb).  Slots: [rhs][chunk][block][sum of the face table lengths],
 // direction MU at offset fo (the lengths before it).
-template <class S, class R, int MU>
+template <class SI, class R, int MU>
 __device__ inline void face_absorb(const int *bface, int fcap, int nf, int fo, int nft, int tid, int NT,
-                                   const void *fx, unsigned qoff, long nfx, long B, int Vbh, R kappa, cx<R> *Rb,
+                                   const void *fx, int qr, long nfx, long B, int Vbh, R kappa, cx<R> *Rb,
                                    cx<R> *Tb) {
     for (int k = tid; k < nf; k += NT) {
         const int ent = bface[MU * fcap + k];
         const int par = ent >> 30, bwd = (ent >> 29) & 1, j = ent & 0x1fffffff;
         cx<R> g[6], a[12];
-        Half<S>::load(fx, nfx, (unsigned)(B * nft + fo + k) + qoff, g);
+        HalfI<SI>::load(fx, nfx, (unsigned)(B * nft + fo + k), qr, g);
         cx<R> *buf = par ? Tb : Rb;
 #pragma unroll
         for (int c = 0; c < 12; ++c) a[c] = buf[c * Vbh + j];
@@ -160,9 +251,9 @@ __device__ inline void face_absorb(const int *bface, int fcap, int nf, int fo, i
 
 // The hops of this block's correction (delta_e in De, delta_o in Do, local
 // index) into the face entries of its neighbours, for direction MU.
-template <class S, class R, int LF, int MU>
+template <class SI, class R, int LF, int MU>
 __device__ inline void face_emit(const int *bface, const int *bfsrc, const int *bfnb, int fcap, int nf, int fo,
-                                 int nft, int tid, int NT, const void *U, void *fx, unsigned qoff, long nfx, long V,
+                                 int nft, int tid, int NT, const void *U, void *fx, int qr, long nfx, long V,
                                  long Vh, long B, int Vbh, const cx<R> *De, const cx<R> *Do) {
     for (int k = tid; k < nf; k += NT) {
         const int ent = bface[MU * fcap + k], src = bfsrc[MU * fcap + k];
@@ -187,7 +278,7 @@ __device__ inline void face_emit(const int *bface, const int *bfsrc, const int *
 #pragma unroll
             for (int c = 0; c < 6; ++c) g[c] = {-g[c].re, -g[c].im};
         }
-        Half<S>::store(fx, nfx, (unsigned)(Rblk * nft + fo + k) + qoff, g);
+        HalfI<SI>::store(fx, nfx, (unsigned)(Rblk * nft + fo + k), qr, g);
     }
 }
 
@@ -202,7 +293,7 @@ enum SweepFlags { SW_FIRST = 1, SW_FACES = 2, SW_STORE_RES = 4, SW_EMIT = 8 };
 // thread still does one site pair of one right-hand side; the vector bases
 // stay wave-uniform and a lane's right-hand side enters through its element
 // index (qr x NCH x V chunks further).
-template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0, int NR = 1>
+template <class S, class R, int LF, int CF, bool LDS, int KS, int MAXT, int VBHC = 0, int NR = 1, class SI = S>
 __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS && MAXT == 256 && VBHC > 0) ? 3 : 1)
     k_sap_sweep(const void *__restrict__ eta_all, void *__restrict__ psi_all, void *__restrict__ res_all,
                 void *__restrict__ fx_all, const void *__restrict__ U, const void *__restrict__ clo,
@@ -227,13 +318,12 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
     const size_t fs = (size_t)Spin<S>::BYTES * V;
     const void *eta = wave_uniform(static_cast<const char *>(eta_all) + (size_t)rg * NR * fs);
     void *psi = wave_uniform(static_cast<char *>(psi_all) + (size_t)rg * NR * fs);
-    void *res = wave_uniform(static_cast<char *>(res_all) + (size_t)rg * NR * fs);
+    void *res = wave_uniform(static_cast<char *>(res_all) + (size_t)rg * NR * VecI<SI>::BYTES * V);
     const unsigned qoff = (unsigned)(qr * Spin<S>::NCH * V);    // its offset, in chunks
     // face exchange: nft entries per block, nfx per chunk plane
     const int fo1 = nface.x, fo2 = fo1 + nface.y, fo3 = fo2 + nface.z, nft = fo3 + nface.w;
     const long nfx = (long)nbc * 2 * nft;
-    void *fx = wave_uniform(static_cast<char *>(fx_all) + (size_t)rg * NR * Half<S>::NCH * 16 * nfx);
-    const unsigned qfx = (unsigned)(qr * Half<S>::NCH * nfx);
+    void *fx = wave_uniform(static_cast<char *>(fx_all) + (size_t)rg * NR * HalfI<SI>::BYTES * nfx);
     const bool first = flags & SW_FIRST;
     const long B = (long)colour * nbc + bx;
     const long boff = B * Vbh;
@@ -254,24 +344,29 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
         if (j < Vbh) {
             const long xe_i = boff + j, xo_i = Vh + boff + j;
             cx<R> e[12];
-            const void *src = first ? eta : res;
-            Spin<S>::load(src, V, xe_i + qoff, e);
+            if (first)
+                Spin<S>::load(eta, V, xe_i + qoff, e);
+            else
+                VecI<SI>::load(res, V, xe_i, qr, e);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Rb[c * Vbh + j] = e[c];
-            Spin<S>::load(src, V, xo_i + qoff, e);
+            if (first)
+                Spin<S>::load(eta, V, xo_i + qoff, e);
+            else
+                VecI<SI>::load(res, V, xo_i, qr, e);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = e[c];
         }
     }
     if (flags & SW_FACES) {
         __syncthreads();
-        face_absorb<S, R, 0>(bface, fcap, nface.x, 0, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
+        face_absorb<SI, R, 0>(bface, fcap, nface.x, 0, nft, tid, NT, fx, qr, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_absorb<S, R, 1>(bface, fcap, nface.y, fo1, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
+        face_absorb<SI, R, 1>(bface, fcap, nface.y, fo1, nft, tid, NT, fx, qr, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_absorb<S, R, 2>(bface, fcap, nface.z, fo2, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
+        face_absorb<SI, R, 2>(bface, fcap, nface.z, fo2, nft, tid, NT, fx, qr, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
-        face_absorb<S, R, 3>(bface, fcap, nface.w, fo3, nft, tid, NT, fx, qfx, nfx, B, Vbh, kappa, Rb, Tb);
+        face_absorb<SI, R, 3>(bface, fcap, nface.w, fo3, nft, tid, NT, fx, qr, nfx, B, Vbh, kappa, Rb, Tb);
         __syncthreads();
     }
     // ---- s_o = A_oo^{-1} rho_o into T; rho_o is parked in the residual
@@ -283,7 +378,7 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
             cx<R> e[12], m[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) e[c] = Tb[c * Vbh + j];
-            Spin<S>::store(res, V, Vh + boff + j + qoff, e);
+            VecI<SI>::store(res, V, Vh + boff + j, qr, e);
             clover_apply<CF>(cinv, Vh, boff + j, e, m);
 #pragma unroll
             for (int c = 0; c < 12; ++c) Tb[c * Vbh + j] = m[c];
@@ -370,7 +465,7 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
                     cx<R> rn[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) rn[c] = cmac(Rb[c * Vbh + j], -alpha, p[k][c]);
-                    Spin<S>::store(res, V, boff + j + qoff, rn);
+                    VecI<SI>::store(res, V, boff + j, qr, rn);
                 }
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
@@ -394,7 +489,7 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
                     rn[c] = Rb[c * Vbh + j];
                     Rb[c * Vbh + j] = {R(0), R(0)};
                 }
-                if (flags & SW_STORE_RES) Spin<S>::store(res, V, boff + j + qoff, rn);
+                if (flags & SW_STORE_RES) VecI<SI>::store(res, V, boff + j, qr, rn);
             }
         }
         __syncthreads();
@@ -410,7 +505,7 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
             const long xe_i = boff + j, xo_i = Vh + boff + j;
             cx<R> acc[12], t[12], q[12];
             block_hop<R, LF, true>(U, lnbr, V, Vh, boff, j, Vbh, Rb, acc);
-            Spin<S>::load(res, V, xo_i + qoff, t);
+            VecI<SI>::load(res, V, xo_i, qr, t);
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = rmac(t[c], kappa, acc[c]);   // u_o
             clover_apply<CF>(cinv, Vh, boff + j, acc, q);                       // delta_o
@@ -425,7 +520,7 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
                 clover_apply<CF>(clo, V, xo_i, q, t);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) t[c] = acc[c] - t[c];
-                Spin<S>::store(res, V, xo_i + qoff, t);
+                VecI<SI>::store(res, V, xo_i, qr, t);
             }
             if (!first) {
                 Spin<S>::load(psi, V, xo_i + qoff, t);
@@ -445,18 +540,18 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
     }
     if (flags & SW_EMIT) {
         __syncthreads();
-        face_emit<S, R, LF, 0>(bface, bfsrc, bfnb, fcap, nface.x, 0, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh, Rb,
+        face_emit<SI, R, LF, 0>(bface, bfsrc, bfnb, fcap, nface.x, 0, nft, tid, NT, U, fx, qr, nfx, V, Vh, B, Vbh, Rb,
                                Tb);
-        face_emit<S, R, LF, 1>(bface, bfsrc, bfnb, fcap, nface.y, fo1, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+        face_emit<SI, R, LF, 1>(bface, bfsrc, bfnb, fcap, nface.y, fo1, nft, tid, NT, U, fx, qr, nfx, V, Vh, B, Vbh,
                                Rb, Tb);
-        face_emit<S, R, LF, 2>(bface, bfsrc, bfnb, fcap, nface.z, fo2, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+        face_emit<SI, R, LF, 2>(bface, bfsrc, bfnb, fcap, nface.z, fo2, nft, tid, NT, U, fx, qr, nfx, V, Vh, B, Vbh,
                                Rb, Tb);
-        face_emit<S, R, LF, 3>(bface, bfsrc, bfnb, fcap, nface.w, fo3, nft, tid, NT, U, fx, qfx, nfx, V, Vh, B, Vbh,
+        face_emit<SI, R, LF, 3>(bface, bfsrc, bfnb, fcap, nface.w, fo3, nft, tid, NT, U, fx, qr, nfx, V, Vh, B, Vbh,
                                Rb, Tb);
     }
 }
 
-template <class S, class R, int LF, int CF>
+template <class S, class R, int LF, int CF, class SI = S>
 static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, int nrhs, hipStream_t s) {
     const Geom &g = f->g;
     const int Vbh = g.Vbh;
@@ -478,10 +573,14 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     }
     // the blocks' stored residuals and the face exchange (half-spinors)
     void *rp;
-    const size_t rbytes = (size_t)Spin<S>::BYTES * g.V * nrhs;
-    const size_t xbytes = (size_t)Half<S>::NCH * 16 * g.Nb * f->nface_tot * nrhs;
+    const size_t rbytes = VecI<SI>::BYTES * g.V * nrhs;
+    const size_t xbytes = HalfI<SI>::BYTES * g.Nb * f->nface_tot * nrhs;
     DFL_TRY(field_buffer(f, BUF_SAP_RES, rbytes + xbytes, &rp));
     void *res = rp, *fx = static_cast<char *>(rp) + rbytes;
+    // the FP16 layouts start a workgroup's second right-hand side at whole
+    // units (V is a product of four even extents; so is every face length)
+    if (sizeof(SI) == 2 && (g.V % 16 || ((long)g.Nb * f->nface_tot) % 2))
+        return set_error(QCD_EINVAL, "FP16 Schwarz vectors need V a multiple of 16");
     const R kappa = (R)f->lat.kappa;
     const int4 nface = make_int4(f->nface[0], f->nface[1], f->nface[2], f->nface[3]);
     const bool pair = sizeof(S) == 4 && f->st_sap_pair && use_lds && Vbh == 128 && NT == 128 && nrhs % 2 == 0;
@@ -494,15 +593,16 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
     //   back substitution and correction h + 576, odd residual 552 (when kept),
     //   this block's hops into the neighbours' faces nf 144 (but the last sweep).
     // Compulsory bytes per pair: eta (first cycle) or the stored residual,
-    // the face half-spinors in (nf B / 2), psi in (after the first cycle) and
-    // out, the stored residual out, the face half-spinors out (nf B / 2); 4
-    // links and the clover term per site, the inverse clover per odd site.
+    // the face half-spinors in (nf of them), psi in (after the first cycle)
+    // and out, the stored residual out, the face half-spinors out; 4 links
+    // and the clover term per site, the inverse clover per odd site.  The
+    // stored residual and the half-spinors take the internal storage type.
     double hops = 0, nf = 0;
     for (int m = 0; m < 4; ++m) {
         hops += 2.0 * (g.b[m] - 1) / g.b[m];
         nf += 4.0 / g.b[m];
     }
-    const double h = 165.0 * hops, B = Spin<S>::BYTES;
+    const double h = 165.0 * hops, B = Spin<S>::BYTES, BI = VecI<SI>::BYTES, BH = HalfI<SI>::BYTES;
     const double lbytes = LF == LNK_F64 ? 144 : (LF == LNK_F16 || LF == LNK_BF16) ? 24 : 48;
     const double cbytes = CF == CLO_F64 ? 576 : CF == CLO_F32 ? 288 : 144;
     const double pairs = (double)nbc * Vbh * nrhs;
@@ -517,8 +617,9 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
             const double fl = pairs * (((flags & SW_FACES) ? nf * 48.0 : 0.0) + 504 + (h + 72) +
                                        nmr * (2 * h + 1392) + (h + 576) + ((flags & SW_STORE_RES) ? 552 : 0) +
                                        ((flags & SW_EMIT) ? nf * 144.0 : 0.0));
-            const double by = pairs * (B * (2 + ((flags & SW_FACES) ? nf / 2 : 0) + (cy == 0 ? 2 : 4) +
-                                            ((flags & SW_STORE_RES) ? 2 : 0) + ((flags & SW_EMIT) ? nf / 2 : 0))) +
+            const double by = pairs * ((cy == 0 ? 2 * B : 2 * BI) + ((flags & SW_FACES) ? nf * BH : 0) +
+                                       B * (cy == 0 ? 2 : 4) + ((flags & SW_STORE_RES) ? 2 * BI : 0) +
+                                       ((flags & SW_EMIT) ? nf * BH : 0)) +
                               (double)nbc * Vbh * 2 * (4 * lbytes + cbytes) + (double)nbc * Vbh * cbytes;
             ProfScope ps(PROF_SAP, s, fl, by, 2 * pairs);
 #define DFL_SAP_ARGS                                                                                             \
@@ -526,7 +627,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
         nface, g.V, g.Vh, Vbh, nbc, col, kappa, nmr, flags, gbuf
 #define DFL_SAP_LAUNCH(LDSV, KSV, MAXT, VBHC)                                                                  \
     {                                                                                                          \
-        auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT, VBHC>;                                          \
+        auto kern = k_sap_sweep<S, R, LF, CF, LDSV, KSV, MAXT, VBHC, 1, SI>;                                   \
         size_t sh = LDSV ? lds : 0;                                                                            \
         if (LDSV && sh > 64 * 1024) (void)hipFuncSetAttribute((const void *)kern,                              \
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
@@ -535,7 +636,7 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
             if constexpr (sizeof(S) == 4) {
                 // two right-hand sides per workgroup (4^4 blocks, even count)
                 if (pair) {
-                    k_sap_sweep<S, R, LF, CF, true, 1, 256, 128, 2><<<dim3(nbc, nrhs / 2), 2 * NT, 2 * lds, s>>>(
+                    k_sap_sweep<S, R, LF, CF, true, 1, 256, 128, 2, SI><<<dim3(nbc, nrhs / 2), 2 * NT, 2 * lds, s>>>(
                         DFL_SAP_ARGS);
                     continue;
                 }
@@ -558,13 +659,21 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
 
 int sap_internal(qcd_field f, const qcd_sap *sap, const void *eta, void *psi, int nrhs, hipStream_t s) {
     if (sap->ncy < 1 || sap->nmr < 0) return set_error(QCD_EINVAL, "SAP needs ncy >= 1 and nmr >= 0");
+    const bool v16 = sap->vecs == QCD_F16;
+    if (v16 && sap->storage != QCD_F16 && sap->storage != QCD_BF16)
+        return set_error(QCD_EINVAL, "FP16 Schwarz vectors go with FP16 or BF16 link storage");
+    const int c = sap->ncy, m = sap->nmr;
     switch (sap->storage) {
-        case QCD_F64: return run_sap<double, double, LNK_F64, CLO_F64>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
-        case QCD_F32: return run_sap<float, float, LNK_F32, CLO_F32>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_F64: return run_sap<double, double, LNK_F64, CLO_F64>(f, c, m, eta, psi, nrhs, s);
+        case QCD_F32: return run_sap<float, float, LNK_F32, CLO_F32>(f, c, m, eta, psi, nrhs, s);
         // FP16 / BF16 link storage enters the Schwarz kernel with row 2
         // precomputed (the same matrices as the reconstruct-12 copies)
-        case QCD_F16: return run_sap<float, float, LNK_F16R, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
-        case QCD_BF16: return run_sap<float, float, LNK_BF16R, CLO_F16>(f, sap->ncy, sap->nmr, eta, psi, nrhs, s);
+        case QCD_F16:
+            return v16 ? run_sap<float, float, LNK_F16R, CLO_F16, __half>(f, c, m, eta, psi, nrhs, s)
+                       : run_sap<float, float, LNK_F16R, CLO_F16>(f, c, m, eta, psi, nrhs, s);
+        case QCD_BF16:
+            return v16 ? run_sap<float, float, LNK_BF16R, CLO_F16, __half>(f, c, m, eta, psi, nrhs, s)
+                       : run_sap<float, float, LNK_BF16R, CLO_F16>(f, c, m, eta, psi, nrhs, s);
         default: return set_error(QCD_EINVAL, "bad SAP storage precision");
     }
 }

@@ -26,6 +26,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 DIMS, BLOCK = (64, 32, 32, 32), (4, 4, 4, 4)
 EPS, KAPPA, CSW = 0.4, 0.124, 1.5
 SAP_TOL_F16 = 1e-5      # FP16 storage: the per-application floor (see test_gpu_ops)
+SAP_TOL_V16 = 5 * 2.0 ** -11   # the sweeps' own vectors in FP16 as well: n_cy u (see test_gpu_ops)
 NB = 24                 # right-hand sides per launch, as in the benchmark
 PHASES = np.exp(1j * np.arange(NB))
 
@@ -117,9 +118,27 @@ def test_fullsize_sap_fp16_storage_batch():
         assert err <= SAP_TOL_F16
 
 
+def test_fullsize_sap_fp16_vectors_batch():
+    """As above with the sweeps' stored residuals and face half-spinors in
+    FP16 as well (the benchmark's sloppy preconditioner)."""
+    torch, dfl = _gpu()
+    s = state()
+    x = batch(np.complex64)
+    psi = dfl.sap_precond(s["fld"], torch.from_numpy(x).cuda(), dfl.SapParams(5, 4, F16, F16)).cpu().numpy()
+    q = quantised_operator(F16)
+    ref = [q.sap(s["base"][k], BLOCK, 5, 4) for k in range(2)]
+    worst = 0.0
+    for r in range(NB):
+        err = rel(psi[r], PHASES[r] * ref[r % 2])
+        worst = max(worst, err)
+        assert err <= SAP_TOL_V16, (r, err)
+    print("fp16-vector sap 32^3x64: worst rel err", worst)
+
+
 def test_fullsize_ama_residuals():
     """The benchmark's solver parameters (deflation N_s = 12, n_inv = 5;
-    sloppy: FP16 storage, residual 3e-3, little budget 4; exact: FP32 SAP,
+    sloppy: FP16 storage and FP16 Schwarz vectors, residual 3e-3, little
+    budget 4; exact: FP32 SAP,
     residual 1e-10, little budget 16; 24 right-hand sides per batch) on two
     source positions of its set, the first also solved exactly.  The
     oracle's FP64 operator recomputes the residual of all 12 spin-colour
@@ -130,7 +149,7 @@ def test_fullsize_ama_residuals():
     x0 = synth.seeded_site(DIMS, 1)
     t0, a0, b0, c0 = (int(v) for v in synth.coords(DIMS, x0))
     positions = [(t0, a0, b0, c0), ((t0 + 16) % 64, a0, b0, (c0 + 16) % 32)]
-    sloppy_sap, exact_sap = dfl.SapParams(5, 4, F16), dfl.SapParams(5, 4, F32)
+    sloppy_sap, exact_sap = dfl.SapParams(5, 4, F16, F16), dfl.SapParams(5, 4, F32)
     d = dfl.Deflation(s["fld"], Ns=12, ninv=5, seed=7, sap=sloppy_sap)
     sloppy = dfl.GcrParams(nkv=8, nmx=24, res=3e-3, sap=sloppy_sap, dfl=d, little_tol=1e-6, little_maxit=4)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=exact_sap, dfl=d, little_tol=1e-10, little_maxit=16)

@@ -11,6 +11,12 @@ bound: both sides build the clover entries independently in FP64, and the
 few entries at an FP16 rounding boundary round to neighbouring values);
 BF16 storage 3e-5 (that floor plus the chain bound of about 30 FP32
 applications at 1e-6 each; observed about 1.1e-5 on the small lattices).
+With the sweeps' own vectors in FP16 (stored block residuals and the
+half-spinors handed across block faces, a power-of-two scale per site) each
+stored vector carries one FP16 rounding, at most u = 2^-11 of its site's
+largest entry; a cycle's stored residual enters the output once, through
+that cycle's corrections, so the bound against the same quantised oracle is
+n_cy u (SAP_TOL_V16).
 """
 
 import numpy as np
@@ -24,6 +30,7 @@ pytestmark = pytest.mark.gpu
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 SAP_TOL = {F32: 1e-6, F16: 1e-5, BF16: 3e-5}
+SAP_TOL_V16 = 5 * 2.0 ** -11
 
 
 def _gpu():
@@ -202,6 +209,42 @@ def test_sap_reduced_precision_matches_quantised_oracle(storage):
     for r in range(2):
         print("sap storage", storage, "rhs", r, "rel err", rel(psi[r], ref[r]))
         assert rel(psi[r], ref[r]) <= SAP_TOL[storage], (r, rel(psi[r], ref[r]))
+
+
+@pytest.mark.parametrize("storage", [F16, BF16])
+def test_sap_fp16_vectors_match_quantised_oracle(storage):
+    """The sweeps' stored residuals and face half-spinors in FP16 (FP32
+    arithmetic, FP32 input and output): the same quantised oracle as the FP32
+    vectors, to n_cy u, on both the paired (4 rhs) and the unpaired kernels;
+    and the FP32-vector result still to its own bound."""
+    torch, dfl = _gpu()
+    c = case(*MID)
+    eta = torch.from_numpy(synth.gaussian_spinor(c.dims, 4, 1007).astype(np.complex64)).cuda()
+    ref = c.qop(storage).sap(eta.cpu().numpy().astype(np.complex128), c.block, 5, 4)
+    out = {}
+    try:
+        for pair in (1, 0):
+            c.field.tune(dfl.Field.TUNE_SAP_PAIR, pair)
+            for vecs in (F32, F16):
+                out[pair, vecs] = dfl.sap_precond(c.field, eta, dfl.SapParams(5, 4, storage, vecs)).cpu().numpy()
+    finally:
+        c.field.tune(dfl.Field.TUNE_SAP_PAIR, 1)
+    for r in range(4):
+        for pair in (1, 0):
+            e16, e32 = rel(out[pair, F16][r], ref[r]), rel(out[pair, F32][r], ref[r])
+            print("sap storage", storage, "pair", pair, "rhs", r, "rel err fp16 vectors", e16, "fp32 vectors", e32)
+            assert e16 <= SAP_TOL_V16, (pair, r, e16)
+            assert e32 <= SAP_TOL[storage], (pair, r, e32)
+
+
+def test_sap_fp16_vectors_refused_with_wide_storage():
+    torch, dfl = _gpu()
+    c = case(*MID)
+    eta = torch.from_numpy(synth.gaussian_spinor(c.dims, 1, 1008).astype(np.complex64)).cuda()
+    for storage in (F64, F32):
+        with pytest.raises(dfl.DflError) as e:
+            dfl.sap_precond(c.field, eta, dfl.SapParams(5, 4, storage, F16))
+        assert e.value.code == -1 and "FP16 Schwarz vectors" in str(e.value)
 
 
 @pytest.mark.parametrize("storage", [F32, F16])
