@@ -6,7 +6,9 @@ synchronisation) and captured, later batches of that size replay the graph.
 A fresh handle solving a replayed batch first (eagerly) is the reference.
 The replays are repeated with eager torch work and synchronisations in
 between, over an uneven mix of Z2-noise and point sources (batches of 4, 4
-and 2), and the residuals they report are checked with the oracle.
+and 2), and the residuals they report are checked with the oracle.  Both
+storage formats of the Schwarz sweeps' own vectors are covered (FP32, and
+the FP16 format of the benchmark's sloppy solves).
 """
 
 import numpy as np
@@ -17,7 +19,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-F16 = 2
+F32, F16 = 1, 2
 DIMS, BLOCK = (8, 8, 8, 8), (4, 4, 4, 4)
 
 
@@ -27,9 +29,9 @@ def _gpu():
     return torch, dfl
 
 
-def make(U, torch, dfl):
+def make(U, torch, dfl, vecs=F32):
     fld = dfl.Field(DIMS, BLOCK, 0.124, 1.5, U)
-    sap = dfl.SapParams(5, 4, F16)
+    sap = dfl.SapParams(5, 4, F16, vecs)
     d = dfl.Deflation(fld, Ns=8, ninv=3, seed=7, sap=sap)
     p = dfl.GcrParams(nkv=4, fixed_iters=2, res=3e-3, sap=sap, dfl=d, little_tol=1e-6, little_maxit=6)
     return fld, d, p
@@ -47,11 +49,12 @@ def sources(torch, dfl, fld):
     return [z[0], pts[0], z[1], pts[1], z[2], pts[2], z[3], pts[3], z[4], pts[4]]
 
 
-def test_graph_replay_matches_eager_solves():
+@pytest.mark.parametrize("vecs", [F32, F16])
+def test_graph_replay_matches_eager_solves(vecs):
     torch, dfl = _gpu()
     U = synth.gauge_field(DIMS, 0.4, 1)
     op = oracle.Operator(DIMS, U, 0.124, 1.5, -1)
-    fld, d, p = make(U, torch, dfl)
+    fld, d, p = make(U, torch, dfl, vecs)
     b = sources(torch, dfl, fld)
     runs = []
     for rep in range(3):
@@ -65,7 +68,7 @@ def test_graph_replay_matches_eager_solves():
         for r in range(10):
             assert np.array_equal(runs[rep][0][r], runs[0][0][r]), (rep, r)
     # reference: a fresh handle computes batch 1 (sources 4..7) eagerly first
-    fld2, d2, p2 = make(U, torch, dfl)
+    fld2, d2, p2 = make(U, torch, dfl, vecs)
     b2 = [b[k].clone() for k in (4, 5, 6, 7)]
     x2, info2 = dfl.gcr_solve_batched(fld2, b2, p2, batch=4, graph=True)
     for k, r in enumerate((4, 5, 6, 7)):

@@ -276,13 +276,23 @@ def test_sap_paired_right_hand_sides(storage):
     ((4, 4, 4, 4), (2, 2, 2, 2)),       # 8 sites per parity in a 64-wide workgroup
 ])
 def test_sap_block_shapes(dims, block):
+    """Every launch shape of the Schwarz sweep, with FP32 storage and with
+    FP16 storage and FP32 or FP16 sweep vectors, against the quantised
+    oracle."""
     torch, dfl = _gpu()
     c = case(dims, block, 0.4, 0.124, 1.5)
     eta = synth.gaussian_spinor(dims, 1, 1005).astype(np.complex64)
-    psi = dfl.sap_precond(c.field, torch.from_numpy(eta).cuda(), dfl.SapParams(5, 4, F32)).cpu().numpy()
+    x = torch.from_numpy(eta).cuda()
+    psi = dfl.sap_precond(c.field, x, dfl.SapParams(5, 4, F32)).cpu().numpy()
     ref = c.qop(F32).sap(eta.astype(np.complex128), block, 5, 4)
     print("sap block", block, "rel err", rel(psi[0], ref[0]))
     assert rel(psi[0], ref[0]) <= SAP_TOL[F32]
+    ref16 = c.qop(F16).sap(eta.astype(np.complex128), block, 5, 4)
+    for vecs, tol in ((F32, SAP_TOL[F16]), (F16, SAP_TOL_V16)):
+        psi = dfl.sap_precond(c.field, x, dfl.SapParams(5, 4, F16, vecs)).cpu().numpy()
+        err = rel(psi[0], ref16[0])
+        print("sap block", block, "fp16 storage, vectors", vecs, "rel err", err)
+        assert err <= tol, (vecs, err)
 
 
 def test_sap_point_source_and_single_cycle():
