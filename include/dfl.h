@@ -283,8 +283,9 @@ typedef struct {
     const unsigned char *exact;    /* host [nsrc] or NULL: nonzero = also solve exactly */
     qcd_gcr sloppy, exact_params;
     qcd_prec sloppy_out;           /* QCD_F64 or QCD_F32 */
-    int batch;                     /* right-hand sides per solver launch (0: library choice); lowered
-                                      (to an even count) only if 90% of the free memory cannot hold it */
+    int batch;                     /* right-hand sides per solver launch (0: library choice, what 60% of
+                                      the available memory holds, at most 48, a multiple of 12 or even);
+                                      a request that 90% cannot hold falls back to that choice */
 } qcd_ama;
 
 int ama_solve(qcd_field f, const qcd_ama *a, void *const *x_sloppy, void *const *x_exact, qcd_prec io,

@@ -91,18 +91,21 @@ def memory_batch_limit(V: int, nkv: int) -> int:
     """Largest batch whose Krylov space (FP32) and FP64 io fit 75% of the
     memory that is free or held by the library's workspace cache (cached
     buffers too small for this lattice are freed when an allocation needs
-    their room)."""
+    their room), rounded down to an even count."""
     import torch
     free, _ = torch.cuda.mem_get_info()
     free += L.workspace_cached(torch.cuda.current_device())
     per = V * (96 * (2 * nkv + 3) + 192 * 5)
-    return max(1, int(0.75 * free) // per)
+    nb = max(1, int(0.75 * free) // per)
+    # the Schwarz and stencil kernels take right-hand sides in pairs
+    return nb - nb % 2 if nb > 1 else nb
 
 
 def sloppy_params(d, fixed_iters: int, res: float = 3e-3) -> L.GcrParams:
-    """The sloppy solve the tuner times: FP16 storage in SAP, a fixed number
-    of outer iterations (no host decisions, so it can be graph-replayed)."""
-    sap = L.SapParams(5, 4, F16)
+    """The sloppy solve the tuner times: FP16 storage and FP16 sweep vectors
+    in SAP, a fixed number of outer iterations (no host decisions, so it can
+    be graph-replayed)."""
+    sap = L.SapParams(5, 4, F16, F16)
     return L.GcrParams(nkv=max(2, fixed_iters), fixed_iters=fixed_iters, res=res, sap=sap, dfl=d,
                        little_tol=1e-6, little_maxit=4)
 
@@ -150,7 +153,7 @@ def tune_solver(dims, U, kappa, csw, nsrc, blocks=((4, 4, 4, 4), (8, 4, 4, 4), (
     site) orders the valid shapes, only the best `keep` of them are timed,
     and the search for N_iter starts at the prior winner's count."""
     log = log or (lambda *a: None)
-    sap = L.SapParams(5, 4, F16)
+    sap = L.SapParams(5, 4, F16, F16)
     V = 1
     for d in dims:
         V *= d

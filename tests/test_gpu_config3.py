@@ -1,6 +1,6 @@
 """The 48^3 x 96 configuration at its stated size: eps 0.4, kappa 0.1245,
-c_sw 1.5, deflation N_s = 20 on 6^4 blocks, BF16 link storage with FP32
-arithmetic in the sloppy solves, FP64 outer GCR; the 12 spin-colour point
+c_sw 1.5, deflation N_s = 20 on 6^4 blocks, BF16 link storage and FP16
+Schwarz vectors with FP32 arithmetic in the sloppy solves, FP64 outer GCR; the 12 spin-colour point
 sources of one position and 12 sequential sources (gamma_5 gamma_3 gamma_5
 insertion on timeslice t0 + 16, section 2.3), each solved sloppily (3e-3)
 and exactly (1e-10).  The sequential sources are built from 12 vectors made
@@ -35,7 +35,7 @@ def test_config3_full_size_point_and_sequential_sets(capsys):
     U = synth.gauge_field(DIMS, 0.4, 1)
     say("gauge field generated")
     fld = dfl.Field(DIMS, BLOCK, KAPPA, CSW, torch.from_numpy(U).cuda())
-    sap_s, sap_e = dfl.SapParams(5, 4, BF16), dfl.SapParams(5, 4, F32)
+    sap_s, sap_e = dfl.SapParams(5, 4, BF16, F16), dfl.SapParams(5, 4, F32)
     d = dfl.Deflation(fld, Ns=20, ninv=5, seed=7, sap=sap_s)
     sloppy = dfl.GcrParams(nkv=8, nmx=30, res=3e-3, sap=sap_s, dfl=d, little_tol=1e-6, little_maxit=4)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap_e, dfl=d, little_tol=1e-10, little_maxit=16)

@@ -1,8 +1,8 @@
 """GPU parity for the other workloads: device-built sources (Z2 noise,
 sequential sources) and the multi-right-hand-side sequential-source workload
 (point sources, then sequential sources gamma_5 gamma_mu gamma_5 at t0 + 16,
-6^4 Schwarz and deflation blocks, N_s = 20, BF16 link storage for the
-sloppy solves, FP64 outer GCR), run at 24^3 x 48 (the smallest lattice of
+6^4 Schwarz and deflation blocks, N_s = 20, BF16 link storage and FP16
+Schwarz vectors for the sloppy solves, FP64 outer GCR), run at 24^3 x 48 (the smallest lattice of
 the uneven multi-field batch) so that the oracle can check it.
 """
 
@@ -84,7 +84,7 @@ def test_sequential_workload_6x4_blocks_ns20_bf16():
     del U
     x0 = synth.seeded_site(dims, 1)
     pos = tuple(int(v) for v in synth.coords(dims, x0))
-    sap_bf, sap_32 = dfl.SapParams(5, 4, BF16), dfl.SapParams(5, 4, F32)
+    sap_bf, sap_32 = dfl.SapParams(5, 4, BF16, F16), dfl.SapParams(5, 4, F32)
     d = dfl.Deflation(fld, Ns=20, ninv=5, seed=7, sap=sap_bf)
     sloppy = dfl.GcrParams(nkv=8, nmx=40, res=3e-3, sap=sap_bf, dfl=d, little_tol=1e-6, little_maxit=8)
     exact = dfl.GcrParams(nkv=16, nmx=400, res=1e-10, sap=sap_32, dfl=d, little_tol=1e-10, little_maxit=16)
