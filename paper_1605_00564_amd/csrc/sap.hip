@@ -522,19 +522,24 @@ __global__ void __launch_bounds__(MAXT, (sizeof(R) == 4 && LF >= LNK_F16 && LDS 
                 for (int c = 0; c < 12; ++c) t[c] = acc[c] - t[c];
                 VecI<SI>::store(res, V, xo_i, qr, t);
             }
+            // both halves of psi are loaded before either is stored, so that
+            // their latencies overlap
+            cx<R> po[12], pe[12];
             if (!first) {
-                Spin<S>::load(psi, V, xo_i + qoff, t);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = q[c] + t[c];
+                Spin<S>::load(psi, V, xo_i + qoff, po);
+                Spin<S>::load(psi, V, xe_i + qoff, pe);
             }
-            Spin<S>::store(psi, V, xo_i + qoff, q);
             if (first) {
+                Spin<S>::store(psi, V, xo_i + qoff, q);
                 Spin<S>::store(psi, V, xe_i + qoff, xe[k]);
             } else {
-                Spin<S>::load(psi, V, xe_i + qoff, q);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) q[c] = q[c] + xe[k][c];
-                Spin<S>::store(psi, V, xe_i + qoff, q);
+                for (int c = 0; c < 12; ++c) {
+                    po[c] = q[c] + po[c];
+                    pe[c] = pe[c] + xe[k][c];
+                }
+                Spin<S>::store(psi, V, xo_i + qoff, po);
+                Spin<S>::store(psi, V, xe_i + qoff, pe);
             }
         }
     }
