@@ -626,9 +626,9 @@ def main():
     ap.add_argument("--sweep-block-ns", default="",
                     help="one AMA step per block shape and N_s, e.g. '4,4,4,4:8,12,20;8,4,4,4:8,12,20'")
     ap.add_argument("--sloppy-storage", type=int, default=F16)
-    ap.add_argument("--sloppy-vecs", type=int, default=F16,
-                    help="storage of the sloppy Schwarz sweeps' own vectors (2 = FP16, 1 = FP32; FP16 needs "
-                         "FP16/BF16 link storage)")
+    ap.add_argument("--sloppy-vecs", type=int, default=None,
+                    help="storage of the sloppy Schwarz sweeps' own vectors (2 = FP16, 1 = FP32; default FP16 "
+                         "with FP16/BF16 link storage, else FP32)")
     ap.add_argument("--batch", type=int, default=24, help="right-hand sides per solver launch (0: from free memory)")
     ap.add_argument("--little-maxit", type=int, default=16,
                     help="little-solve iterations inside P_R for the exact solves")
@@ -702,6 +702,8 @@ def main():
     del U
     log(f"[bench] gauge field generated and uploaded in {time.perf_counter() - t:.1f} s")
 
+    if args.sloppy_vecs is None:
+        args.sloppy_vecs = F16 if args.sloppy_storage in (F16, BF16) else F32
     sap_sloppy = dfl.SapParams(5, 4, args.sloppy_storage, args.sloppy_vecs)
     sap_exact = dfl.SapParams(5, 4, F32)
     # sloppy solutions stored in FP32, exact ones in FP64
