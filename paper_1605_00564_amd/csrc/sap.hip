@@ -28,6 +28,9 @@
 // writing, for every face site of its neighbours, the link times the spin
 // projection of its delta (a half-spinor), in the order of the neighbour's
 // face table, so the neighbour's next sweep reads them contiguously.
+// The stored residuals and the half-spinors take the sweep's own storage
+// type SI (the arithmetic type, or FP16 with a power-of-two scale per site);
+// eta and psi keep the arithmetic type.
 // The first cycle starts from rho = eta (psi = 0).  The face hops of a block
 // are listed per direction mu (block-face table, the same for every block):
 // all threads of the workgroup take one direction per round, so no two of
