@@ -180,6 +180,24 @@ def test_multi_field_call_equals_per_field_calls():
             assert oracle.norm(b[j] - op2.M(x[j])) / oracle.norm(b[j]) <= 3e-3
 
 
+def test_oversized_batch_request_falls_back_to_the_library_choice():
+    """A batch request that memory cannot hold is not an error: the library
+    takes its own choice (what 60% of the available memory holds, at most
+    48), so the solutions equal those of an unrequested batch bit for bit."""
+    torch, dfl = _gpu()
+    op, fld = field()
+    sloppy = dfl.GcrParams(nkv=8, nmx=30, res=3e-3, sap=dfl.SapParams(5, 4, F16, F16))
+    exact = dfl.GcrParams(nkv=16, nmx=300, res=1e-10, sap=dfl.SapParams(5, 4, F32))
+    srcs = library_sources(torch, dfl, [dict(kind="point", pos=(1, 2, 3, 0)), dict(kind="z2", seed=4, index=0,
+                                                                                    nvec=3)])
+    big = dfl.ama_solve(fld, srcs, [True, False], sloppy, exact, dtype=torch.complex128, batch=10 ** 6)
+    ref = dfl.ama_solve(fld, srcs, [True, False], sloppy, exact, dtype=torch.complex128, batch=0)
+    for a, b in zip(big[0] + big[1], ref[0] + ref[1]):
+        assert torch.equal(a, b)
+    assert all(i.status == 0 for i in big[2] + big[3])
+    assert [i.rel_res for i in big[2] + big[3]] == [i.rel_res for i in ref[2] + ref[3]]
+
+
 def test_invalid_sets_are_rejected_before_any_solve():
     torch, dfl = _gpu()
     op, fld = field()
