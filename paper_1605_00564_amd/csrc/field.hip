@@ -6,6 +6,7 @@
 #include <mutex>
 
 #include "internal.h"
+#include "block_tables.h"
 
 namespace dfl {
 
@@ -716,87 +717,17 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         (void)hipGetLastError();
         return fail(set_error(QCD_ENOMEM, "pinned host allocation failed"));
     }
-    // in-block neighbour table of the block shape (local lexicographic index l,
-    // parity of l's coordinates, j = l >> 1)
-    std::vector<short> lnb((size_t)16 * g.Vbh, -1);
-    for (int l = 0; l < g.Vb; ++l) {
-        int c[4], r = l;
-        for (int m = 3; m >= 0; --m) {
-            c[m] = r % g.b[m];
-            r /= g.b[m];
-        }
-        const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-        for (int mu = 0; mu < 4; ++mu)
-            for (int d = 0; d < 2; ++d) {
-                int cc[4] = {c[0], c[1], c[2], c[3]};
-                cc[mu] += d == 0 ? 1 : -1;
-                if (cc[mu] < 0 || cc[mu] >= g.b[mu]) continue;
-                int l2 = 0;
-                for (int m = 0; m < 4; ++m) l2 = l2 * g.b[m] + cc[m];
-                lnb[((size_t)p * g.Vbh + (l >> 1)) * 8 + 2 * mu + d] = (short)(l2 >> 1);
-            }
-    }
+    // in-block neighbours, face lists and their sources, block order and the
+    // face-exchange neighbours (block_tables.h)
+    BlockTables bt;
+    build_block_tables(g.b, g.nb, lat->bc_t, bt);
     if (g.Vbh > 32767) return fail(set_error(QCD_EINVAL, "Schwarz block too large"));
-    // hops that leave a block, grouped by direction mu: the forward-face
-    // sites (both parities) first, then the backward-face ones; the two
-    // faces of one mu are disjoint because block extents are at least 2
-    std::vector<int> face[4];
-    for (int mu = 0; mu < 4; ++mu)
-        for (int d = 0; d < 2; ++d)
-            for (int l = 0; l < g.Vb; ++l) {
-                int c[4], r = l;
-                for (int m = 3; m >= 0; --m) {
-                    c[m] = r % g.b[m];
-                    r /= g.b[m];
-                }
-                if (c[mu] != (d == 0 ? g.b[mu] - 1 : 0)) continue;
-                const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-                face[mu].push_back((p << 30) | (d << 29) | (l >> 1));
-            }
-    // within a face, parity-major and ascending j: consecutive lanes then
-    // read consecutive exchange-buffer rows of one parity (no bank conflicts)
-    for (int mu = 0; mu < 4; ++mu) std::sort(face[mu].begin(), face[mu].end(), [](int a, int b) {
-        const int da = (a >> 29) & 1, db = (b >> 29) & 1;
-        return da != db ? da < db : a < b;
-    });
-    f->face_cap = 0;
-    for (int mu = 0; mu < 4; ++mu) {
-        f->nface[mu] = (int)face[mu].size();
-        f->face_cap = std::max(f->face_cap, f->nface[mu]);
-    }
-    std::vector<int> fl((size_t)4 * f->face_cap, 0);
-    for (int mu = 0; mu < 4; ++mu) std::copy(face[mu].begin(), face[mu].end(), fl.begin() + (size_t)mu * f->face_cap);
-    // the source of each face entry: x on the forward face (d = 0) is fed by
-    // x + mu, the site with c_mu = 0 in the next block; x on the backward
-    // face by x - mu, the site with c_mu = b_mu - 1 in the previous block
-    std::vector<int> fsrc((size_t)4 * f->face_cap, 0);
-    f->nface_tot = 0;
-    for (int mu = 0; mu < 4; ++mu) {
-        f->nface_tot += f->nface[mu];
-        for (int k = 0; k < f->nface[mu]; ++k) {
-            const int ent = face[mu][k], par = ent >> 30, d = (ent >> 29) & 1, j = ent & 0x1fffffff;
-            int c[4], l = -1;
-            for (int cand = 2 * j; cand <= 2 * j + 1 && l < 0; ++cand) {
-                int r = cand, sum = 0;
-                for (int m = 3; m >= 0; --m) {
-                    c[m] = r % g.b[m];
-                    r /= g.b[m];
-                    sum += c[m];
-                }
-                if ((sum & 1) == par) l = cand;
-            }
-            c[mu] = d == 0 ? 0 : g.b[mu] - 1;
-            int l2 = 0, sum = 0;
-            for (int m = 0; m < 4; ++m) {
-                l2 = l2 * g.b[m] + c[m];
-                sum += c[m];
-            }
-            fsrc[(size_t)mu * f->face_cap + k] = ((sum & 1) << 30) | (l2 >> 1);
-        }
-    }
-    if (!dev_alloc(f->device, (void **)&f->bface, sizeof(int) * fl.size()) ||
-        !dev_alloc(f->device, (void **)&f->bfsrc, sizeof(int) * fsrc.size()) ||
-        !dev_alloc(f->device, (void **)&f->bfnb, sizeof(int) * 8 * (size_t)g.Nb))
+    f->face_cap = bt.face_cap;
+    for (int mu = 0; mu < 4; ++mu) f->nface[mu] = bt.nface[mu];
+    f->nface_tot = bt.nface_tot;
+    if (!dev_alloc(f->device, (void **)&f->bface, sizeof(int) * bt.fl.size()) ||
+        !dev_alloc(f->device, (void **)&f->bfsrc, sizeof(int) * bt.fsrc.size()) ||
+        !dev_alloc(f->device, (void **)&f->bfnb, sizeof(int) * bt.fnb.size()))
         return fail(set_error(QCD_ENOMEM, "device allocation failed in qcd_field_create"));
     // stencil launch defaults, overridable from the environment
     if (const char *e = getenv("DFL_STENCIL_BLOCK")) f->st_block = atoi(e);
@@ -808,42 +739,14 @@ static int field_create_common(const qcd_lattice *lat, const double2 *canon, hip
         const int v = atoi(e);
         f->st_nr = v == 1 || v == 2 || v == 4 ? v : 0;
     }
-    // blocks in lexicographic order -> their place in the colour-major layout
-    std::vector<int> bord(g.Nb);
-    for (int Bl = 0; Bl < g.Nb; ++Bl) {
-        int r = Bl, bsum = 0;
-        for (int m = 3; m >= 0; --m) {
-            bsum += r % g.nb[m];
-            r /= g.nb[m];
-        }
-        bord[Bl] = (bsum & 1) * (g.Nb / 2) + Bl / 2;
-    }
-    // block neighbours for the face exchange of the Schwarz sweeps
-    std::vector<int> fnb((size_t)8 * g.Nb);
-    for (int Bl = 0; Bl < g.Nb; ++Bl) {
-        int cb[4], r = Bl;
-        for (int m = 3; m >= 0; --m) {
-            cb[m] = r % g.nb[m];
-            r /= g.nb[m];
-        }
-        for (int mu = 0; mu < 4; ++mu)
-            for (int d = 0; d < 2; ++d) {
-                int cc[4] = {cb[0], cb[1], cb[2], cb[3]};
-                cc[mu] = (cc[mu] + (d == 0 ? -1 : 1) + g.nb[mu]) % g.nb[mu];
-                int Rl = 0;
-                for (int m = 0; m < 4; ++m) Rl = Rl * g.nb[m] + cc[m];
-                // d = 0: the reader's forward face meets this block's first
-                // time slice; d = 1: its backward face meets the last one
-                const bool wrap = mu == 0 && (d == 0 ? cb[0] == 0 : cb[0] == g.nb[0] - 1);
-                fnb[(size_t)bord[Bl] * 8 + 2 * mu + d] =
-                    bord[Rl] | ((wrap && lat->bc_t == -1) ? (int)0x80000000u : 0);
-            }
-    }
-    hipError_t e = hipMemcpyAsync(f->lnbr, lnb.data(), sizeof(short) * lnb.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->bface, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->bfsrc, fsrc.data(), sizeof(int) * fsrc.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->bfnb, fnb.data(), sizeof(int) * fnb.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(f->border, bord.data(), sizeof(int) * bord.size(), hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(f->lnbr, bt.lnb.data(), sizeof(short) * bt.lnb.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f->bface, bt.fl.data(), sizeof(int) * bt.fl.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->bfsrc, bt.fsrc.data(), sizeof(int) * bt.fsrc.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->bfnb, bt.fnb.data(), sizeof(int) * bt.fnb.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f->border, bt.bord.data(), sizeof(int) * bt.bord.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(f->flag, 0, sizeof(int), s);
     if (e != hipSuccess) return fail(set_error(QCD_EHIP, std::string("field setup: ") + hipGetErrorString(e)));
     {
