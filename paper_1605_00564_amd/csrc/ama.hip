@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "batch_rule.h"
 #include "blas.h"
 
 namespace dfl {
@@ -43,19 +44,7 @@ int pick_batch(qcd_field f, const qcd_gcr &p, int want, int busy) {
         if (k != busy) freeb += f->buf_bytes[k];
     const size_t V = f->g.V;
     const size_t inner = p.sap.storage == QCD_F64 ? 192 : 96;
-    const size_t per = std::max<size_t>(V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5), 1);
-    // a request that 90% of the available memory holds is kept; otherwise
-    // the batch is what 60% holds (at most 48, a multiple of 12 when
-    // possible, else even: the Schwarz and stencil kernels pair right-hand
-    // sides), so that the caller keeps room for its own allocations
-    if (want > 0 && (size_t)want <= (size_t)(0.9 * (double)freeb) / per) return want;
-    size_t n = std::min<size_t>(std::max<size_t>((size_t)(0.6 * (double)freeb) / per, 1), 48);
-    if (want > 0) n = std::min<size_t>(n, (size_t)want);
-    if (n >= 12)
-        n -= n % 12;
-    else if (n > 1)
-        n -= n % 2;
-    return (int)n;
+    return batch_rule(freeb, V * (inner * (2 * (size_t)p.nkv + 3) + 192 * 5), want);
 }
 
 namespace {
