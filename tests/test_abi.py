@@ -132,3 +132,43 @@ def test_lattice_checks_come_before_any_device_call():
     rc, msg, _ = _create(lib, (112, 56, 56, 56), (4, 4, 4, 4))
     assert rc == -1 and "32-bit buffer offsets" in msg
     assert 96 * 48 ** 3 * 384 < 2 ** 32 <= 112 * 56 ** 3 * 384
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the parameter structs have the C header's sizes
+    and field offsets (a host program built against include/dfl.h prints
+    them)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_1605_00564_amd import _lib as L
+
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    mirrors = {"qcd_lattice": L._Lattice, "qcd_sap": L._Sap, "qcd_dfl_params": L._DflParams, "qcd_gcr": L._Gcr,
+               "qcd_info": L._Info, "qcd_source": L._Source, "qcd_ama": L._Ama}
+    lines = ["#include <cstddef>", "#include <cstdio>", '#include "dfl.h"', "int main() {"]
+    for cname, py in mirrors.items():
+        lines.append(f'    std::printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    std::printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                        "-I" + os.path.join(root, "include"), str(src), "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0 and "hip_runtime_api.h" in r.stderr:
+        pytest.skip("HIP headers not available")
+    assert r.returncode == 0, r.stderr
+    out = [v for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n") if v]
+    assert len(out) == sum(len(py._fields_) + 1 for py in mirrors.values())
+    for line in out:
+        parts = line.split()
+        py = mirrors[parts[0]]
+        if parts[1] == "size":
+            assert ctypes.sizeof(py) == int(parts[2]), line
+        else:
+            assert getattr(py, parts[1]).offset == int(parts[2]), line
