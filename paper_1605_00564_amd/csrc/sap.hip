@@ -653,6 +653,9 @@ static int run_sap(qcd_field f, int ncy, int nmr, const void *eta, void *psi, in
                 if (Vbh == 128) DFL_SAP_LAUNCH(true, 1, 256, 128)
                 else if (Vbh == 256) DFL_SAP_LAUNCH(true, 1, 256, 256)
                 else if (NT <= 256) DFL_SAP_LAUNCH(true, 1, 256, 0)
+                // a bound of 768 threads (e.g. 6^4 blocks, 704) leaves 168
+                // registers per lane where 1024 would cap them at 128
+                else if (NT <= 768) DFL_SAP_LAUNCH(true, 1, 768, 0)
                 else DFL_SAP_LAUNCH(true, 1, 1024, 0)
             } else {
                 if (KS == 1) DFL_SAP_LAUNCH(false, 1, 1024, 0)
